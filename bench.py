@@ -1,0 +1,186 @@
+"""Benchmark: streaming TVOLAP throughput on one MI355X.
+
+A step is one pass of the whole hot path over the workload's signal: every
+block of the 5 s (binaural) input runs through window + transform-in, the
+spectral MAC against the partition spectra of the slot selected for that block,
+transform-out and overlap-add, for all channels. Inputs, IR bank, schedule and
+outputs are resident in HBM before timing starts.
+
+Prints one JSON line (see the keys below) with the roofline of the spectral-MAC
+kernel (HIP events around every MAC launch over the timed region) and a CPU
+baseline (the FP64 oracle on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "binaural": dict(desc="64 sources x 2 ears = 128 channels, L=256 (blocks 512, FFT 1024), 96000-tap IRs "
+                          "(188 partitions), 4 IR slots per channel switched every block, 5 s at 48 kHz",
+                     fn="binaural", dtype="f32"),
+    "binaural_bf16": dict(desc="as binaural, IR spectra and delay line stored bf16", fn="binaural", dtype="bf16"),
+    "binaural_f16": dict(desc="as binaural, IR spectra and delay line stored f16", fn="binaural", dtype="f16"),
+    "uneven": dict(desc="512 channels, L=128, IR lengths log-uniform 4800..192000 taps, 2 slots, "
+                        "each channel toggles with p=0.1 per block, 2 s at 48 kHz", fn="uneven", dtype="f32"),
+    "plain": dict(desc="1 channel, L=128, 4096-tap IRs, 2 slots switched every 50 blocks, 10 s at 48 kHz",
+                  fn="plain", dtype="f32"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, budget_s: float) -> dict:
+    """FP64 oracle on the first channels of the workload until the budget is spent."""
+    import oracle as orc
+
+    x = wl.padded_input().astype(np.float64)
+    t_wall = time.perf_counter()
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    done = 0
+    for c in range(wl.n_channels):
+        H = orc.channel_spectra([t.astype(np.float64) for t in wl.taps[c]], wl.hop, int(wl.taps_of_channel[c]))
+        orc.tvolap_stream(x[wl.input_of_channel[c]], H, wl.schedule[:, c], wl.hop, wl.n_calls)
+        done += 1
+        if time.perf_counter() - t_wall > budget_s:
+            break
+    wall = time.perf_counter() - t_wall
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    samples = done * wl.n_calls * wl.hop
+    return {"value": samples / wall, "unit": "channel-samples/s", "cores": max(1, int(round(cpu / wall))),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, first {done} of {wl.n_channels} channels over the full "
+                      f"{wl.n_calls}-block stream ({wall:.1f} s wall, {cpu:.1f} s CPU)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="binaural", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); channels are independent, "
+              "so more GPUs would shard channels with no communication", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2310_00319_amd import Convolver
+
+    spec = WORKLOADS[args.workload]
+    log(f"workload {args.workload}: {spec['desc']}")
+    t0 = time.perf_counter()
+    wl = getattr(synth, spec["fn"])()
+    log(f"generated in {time.perf_counter() - t0:.1f} s: C={wl.n_channels} I={wl.n_inputs} L={wl.hop} "
+        f"calls={wl.n_calls}")
+    torch.cuda.set_device(0)
+    conv = Convolver(hop=wl.hop, n_channels=wl.n_channels, max_taps=wl.max_taps(), n_inputs=wl.n_inputs,
+                     input_of_channel=wl.input_of_channel, taps_of_channel=wl.taps_of_channel,
+                     n_slots=wl.n_slots, dtype=spec["dtype"])
+    t0 = time.perf_counter()
+    for c in range(wl.n_channels):
+        for s in range(wl.n_slots):
+            conv.set_ir(c, s, wl.taps[c][s])
+    torch.cuda.synchronize()
+    t_setir = time.perf_counter() - t0
+    info = conv.info()
+    log(f"IR bank loaded in {t_setir:.2f} s; info {info}")
+
+    x = torch.from_numpy(wl.padded_input()).cuda()
+    sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
+    out = torch.empty((wl.n_channels, wl.n_calls * wl.hop), device="cuda", dtype=torch.float32)
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        conv.process(x, sched, out)
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup} done")
+
+    if not args.no_kernel_timing:
+        conv.set_timing(True)
+        conv.get_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        conv.process(x, sched, out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    timing = conv.get_timing() if not args.no_kernel_timing else None
+    conv.set_timing(False)
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    blocks = wl.n_calls
+    ch_samples = wl.n_channels * blocks * wl.hop
+    value = ch_samples / (ms_per_step / 1e3)
+    us_per_block = 1e3 * ms_per_step / blocks
+    rtf = (wl.hop / wl.fs) / (us_per_block * 1e-6)
+
+    roof = None
+    if timing and timing["blocks"] > 0:
+        mac_ms = timing["ms_mac"] / timing["blocks"]
+        achieved = info["mac_bytes_per_block"] / (mac_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_mac (spectral MAC, eq. 8)",
+                "bytes_per_launch": info["mac_bytes_per_block"],
+                "avg_launch_us": round(mac_ms * 1e3, 3),
+                "phase_us_per_block": {"in": round(1e3 * timing["ms_in"] / timing["blocks"], 3),
+                                       "mac": round(1e3 * mac_ms, 3),
+                                       "out": round(1e3 * timing["ms_out"] / timing["blocks"], 3)}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(wl, args.cpu_budget)
+
+    res = {
+        "metric": "channel-samples/s at L=256, 2-s IRs (FP32 vs BF16/batched); % HBM peak",
+        "value": round(value, 1),
+        "unit": "channel-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": spec["dtype"],
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {spec['desc']}", "channels": wl.n_channels,
+                   "inputs": wl.n_inputs, "hop": wl.hop, "ir_taps": int(wl.max_taps()),
+                   "partitions_total": info["sum_partitions"], "blocks_per_step": blocks,
+                   "spectra_dtype": spec["dtype"]},
+        "us_per_block": round(us_per_block, 3),
+        "real_time_factor": round(rtf, 1),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "ir_bank_load_s": round(t_setir, 3),
+    }
+    conv.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * tvolap.h - C ABI of the MI355X (gfx950) TVOLAP library.
+ *
+ * Time-Variant Overlap-Add in Partitions (Jaeger, Simmer, Bitzer, Blau,
+ * arXiv 2310.00319). Per channel and per block of L new samples the library
+ *   - weights the last 2L input samples with a periodic Hann window of
+ *     amplitude 1/2 (Sec. 2, eq. 1-2; the windows at hop L sum to one),
+ *   - zero pads the block to 4L and transforms it (eq. 4-5),
+ *   - keeps the spectra of past blocks in a frequency-domain delay line and
+ *     multiplies every second one with the 4L-point spectra of the impulse
+ *     response's 2L-tap partitions (eq. 3, 6-8),
+ *   - transforms the sum back (eq. 9) and overlap-adds the 4L-sample result at
+ *     hop L (eq. 10-13, each block's right half meeting the left half of the
+ *     block two hops later).
+ * An impulse-response switch exchanges all partition spectra of a channel at a
+ * block boundary (end of Sec. 2); many channels run in parallel.
+ *
+ * Conventions for every entry point:
+ *   - Return value: TVOLAP_OK (0) or a negative error code. On an error the
+ *     handle's state is unchanged and tvolap_last_error() describes it.
+ *     No C++ exception crosses this interface.
+ *   - Device pointers are HIP device allocations on the handle's device. All
+ *     device work is enqueued on the handle's stream and is asynchronous with
+ *     respect to the host unless stated otherwise.
+ *   - A handle is used by one host thread at a time.
+ *   - Sample and spectrum values are float32 in device memory.
+ */
+#ifndef TVOLAP_H
+#define TVOLAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TVOLAP_OK 0
+#define TVOLAP_EINVAL (-1)   /* invalid argument                                   */
+#define TVOLAP_ENOMEM (-2)   /* device or host allocation failed                   */
+#define TVOLAP_EDEVICE (-3)  /* a HIP call failed; message in tvolap_last_error()  */
+#define TVOLAP_ESTATE (-4)   /* call not valid in the handle's current state       */
+
+/* Storage type of the partition spectra and of the delay line. Transforms and
+ * accumulation are float32 for every choice; bf16 and f16 are rounded to
+ * nearest even from float32 when stored. */
+typedef enum { TVOLAP_F32 = 0, TVOLAP_BF16 = 1, TVOLAP_F16 = 2 } tvolap_dtype;
+
+typedef struct tvolap tvolap_t;
+
+typedef struct {
+  int32_t hop;                      /* L: block hop in samples, one of 64, 128, 256, 512.
+                                       Input blocks and IR partitions are 2L long,
+                                       transforms 4L long (Sec. 2).                      */
+  int32_t n_channels;               /* C >= 1: convolution channels (outputs).          */
+  int32_t n_inputs;                 /* I >= 1: distinct input signals.                   */
+  const int32_t* input_of_channel;  /* host [C], values in [0, I); NULL = identity
+                                       (then I must equal C). Channels that share an
+                                       input share its delay line.                       */
+  int32_t max_taps;                 /* >= 1: longest impulse response of any channel.    */
+  const int32_t* taps_of_channel;   /* host [C] IR length per channel (all its slots),
+                                       1 .. max_taps; NULL = max_taps for every channel.
+                                       Channel c has M_c = ceil(taps_c / 2L) partitions. */
+  int32_t n_slots;                  /* K >= 1: impulse-response slots per channel.       */
+  int32_t spectra_dtype;            /* tvolap_dtype.                                     */
+  void* stream;                     /* hipStream_t for all device work; NULL = the null
+                                       stream.                                           */
+} tvolap_config;
+
+/* Sizes of a handle, for accounting. Bytes count what one processed block must
+ * move at least: every active partition spectrum once, every delay-line
+ * spectrum once per input, the new spectra written, the input and output
+ * samples. */
+typedef struct {
+  int32_t hop, n_channels, n_inputs, n_slots, spectra_dtype;
+  int32_t bins;                     /* 2L complex values per stored spectrum (the DC and
+                                       Nyquist bins, both real, share one complex slot). */
+  int64_t sum_partitions;           /* sum over channels of M_c                          */
+  int64_t sum_input_partitions;     /* sum over inputs of the delay-line length M_i      */
+  int64_t mac_bytes_per_block;      /* spectral MAC: IR + delay-line spectra read        */
+  int64_t block_bytes;              /* whole block: MAC + new spectra + samples in/out   */
+  int64_t bank_bytes, delay_line_bytes, workspace_bytes;
+  int32_t n_work_items;             /* MAC work items per block                          */
+  int32_t mac_chunk;                /* partitions per MAC work item                      */
+  int32_t mac_waves;                /* waves per MAC workgroup                           */
+  int32_t mac_grid;                 /* MAC workgroups launched (persistent grid size)    */
+} tvolap_info;
+
+/* Create a convolver (Sec. 2: partitioned, block-synchronously switchable,
+ * multichannel). Allocates on the current HIP device: the IR bank
+ * [C][K][M_c][2L], the delay line [I][2][M_i][2L] (M_i = max M_c over the
+ * channels fed by input i), input history, overlap-add state, and tables
+ * (twiddles and window computed in double precision on the host). The bank is
+ * zeroed (all slots hold a zero IR), the stream state is reset and every
+ * channel selects slot 0. Synchronous. *out receives the handle, or NULL on an
+ * error. Errors: EINVAL (bad sizes, hop not supported, map out of range),
+ * ENOMEM, EDEVICE. */
+int tvolap_create(const tvolap_config* cfg, tvolap_t** out);
+
+/* Free every allocation of the handle after waiting for its stream. NULL is
+ * accepted. */
+int tvolap_destroy(tvolap_t* h);
+
+/* Load an impulse response into slot `slot` of channel `channel` (Sec. 2,
+ * eq. 3, 6-7): the taps are cut into M_c partitions of 2L taps (taps beyond
+ * n_taps are zero), each partition is zero padded to 4L and transformed, and
+ * the spectra are stored in the bank. `taps` is host memory (copied before
+ * the call returns) or, if taps_on_device != 0, a device array read in stream
+ * order. If the slot is the channel's active slot the new IR takes effect at
+ * the next processed block, for all partitions at once.
+ * Errors: EINVAL (channel/slot out of range, n_taps < 0 or > taps of the
+ * channel, NULL taps with n_taps > 0). n_taps == 0 stores a zero IR. */
+int tvolap_set_ir(tvolap_t* h, int32_t channel, int32_t slot, const float* taps,
+                  int32_t n_taps, int32_t taps_on_device);
+
+/* Select the active slot of every channel (end of Sec. 2: all partitions of a
+ * channel switch together). `slot_of_channel` is a host array [C] with values
+ * in [0, K); it is copied before the call returns and applies from the next
+ * processed block on. Errors: EINVAL (NULL, value out of range). */
+int tvolap_select_ir(tvolap_t* h, const int32_t* slot_of_channel);
+
+/* Process one block (Sec. 2, eq. 1-13; Fig. 2). `in` is a device array holding
+ * L new samples of every input, input i at in[i*in_stride + n], n < L; `out`
+ * receives L samples of every channel at out[c*out_stride + n]. Strides are in
+ * floats, >= L. Call number c (counting from creation or the last reset)
+ * consumes input samples [cL, (c+1)L), completes input block c - 1 (covering
+ * [(c-1)L, (c+1)L)) and emits output samples [(c-1)L, cL): the stream is the
+ * time-variant convolution delayed by L samples (with the L samples of
+ * buffering, an input-to-output latency of 2L, Sec. 3 Table 1).
+ * `slot_of_channel_dev` is NULL (use the current selection) or a device array
+ * [C] of slots for this block, read in stream order; it also becomes the
+ * current selection. Values outside [0, K) are clamped into range.
+ * Errors: EINVAL (NULL in/out, stride < L). */
+int tvolap_process_block(tvolap_t* h, const float* in, int64_t in_stride, float* out,
+                         int64_t out_stride, const int32_t* slot_of_channel_dev);
+
+/* Zero the delay line, the input history and the overlap-add state and
+ * restart the call count (the bank and the selection are kept). Stream
+ * ordered. */
+int tvolap_reset(tvolap_t* h);
+
+/* Fill *info (host). */
+int tvolap_get_info(const tvolap_t* h, tvolap_info* info);
+
+/* Partition count M_c of every channel into the host array m_of_channel [C]. */
+int tvolap_get_partitions(const tvolap_t* h, int32_t* m_of_channel);
+
+/* Kernel timing. With enable != 0, every processed block records HIP events
+ * on the handle's stream around its kernels. tvolap_get_timing waits for the
+ * recorded blocks and returns the summed milliseconds of the transform-in,
+ * spectral-MAC and transform-out phases and the number of blocks they cover,
+ * then clears the sums. Phases that run fused inside one kernel report their
+ * time under the MAC. */
+int tvolap_set_timing(tvolap_t* h, int32_t enable);
+int tvolap_get_timing(tvolap_t* h, double* ms_in, double* ms_mac, double* ms_out,
+                      int64_t* n_blocks);
+
+/* Message describing the last error of `h`, or of the last failed
+ * tvolap_create when h is NULL. Never NULL. */
+const char* tvolap_last_error(const tvolap_t* h);
+
+/* Library version string. */
+const char* tvolap_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVOLAP_H */

@@ -1,0 +1,140 @@
+"""ctypes declarations for libtvolap.so (the C ABI in include/tvolap.h).
+
+The library links against libamdhip64.so.7. PyTorch's ROCm build ships a HIP
+runtime with the same soname; importing torch first makes the dynamic loader
+bind the library to that one runtime, so device pointers and streams created by
+torch are valid inside the library. ``load()`` checks that exactly one HIP
+runtime is mapped into the process and fails loudly otherwise, and fails
+loudly when the library has not been built. There is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must be loaded before the library, see above)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtvolap.so")
+
+TVOLAP_OK = 0
+TVOLAP_EINVAL = -1
+TVOLAP_ENOMEM = -2
+TVOLAP_EDEVICE = -3
+TVOLAP_ESTATE = -4
+
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+
+EXPORTED = (
+    "tvolap_create", "tvolap_destroy", "tvolap_set_ir", "tvolap_select_ir",
+    "tvolap_process_block", "tvolap_reset", "tvolap_get_info", "tvolap_get_partitions",
+    "tvolap_set_timing", "tvolap_get_timing", "tvolap_last_error", "tvolap_version",
+)
+
+
+class TvolapConfig(ctypes.Structure):
+    _fields_ = [
+        ("hop", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("n_inputs", ctypes.c_int32),
+        ("input_of_channel", ctypes.POINTER(ctypes.c_int32)),
+        ("max_taps", ctypes.c_int32),
+        ("taps_of_channel", ctypes.POINTER(ctypes.c_int32)),
+        ("n_slots", ctypes.c_int32),
+        ("spectra_dtype", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class TvolapInfo(ctypes.Structure):
+    _fields_ = [
+        ("hop", ctypes.c_int32), ("n_channels", ctypes.c_int32), ("n_inputs", ctypes.c_int32),
+        ("n_slots", ctypes.c_int32), ("spectra_dtype", ctypes.c_int32),
+        ("bins", ctypes.c_int32),
+        ("sum_partitions", ctypes.c_int64),
+        ("sum_input_partitions", ctypes.c_int64),
+        ("mac_bytes_per_block", ctypes.c_int64),
+        ("block_bytes", ctypes.c_int64),
+        ("bank_bytes", ctypes.c_int64),
+        ("delay_line_bytes", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_int64),
+        ("n_work_items", ctypes.c_int32),
+        ("mac_chunk", ctypes.c_int32),
+        ("mac_waves", ctypes.c_int32),
+        ("mac_grid", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TvolapError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tvolap error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def _hip_runtimes_mapped() -> list:
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) >= 6 and "libamdhip64.so" in parts[-1]:
+                    paths.add(os.path.realpath(parts[-1]))
+    except OSError:
+        pass
+    return sorted(paths)
+
+
+def _declare(lib):
+    c_int, c_i32, c_i64, c_vp = ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.tvolap_create.argtypes = [ctypes.POINTER(TvolapConfig), ctypes.POINTER(c_vp)]
+    lib.tvolap_destroy.argtypes = [c_vp]
+    lib.tvolap_set_ir.argtypes = [c_vp, c_i32, c_i32, c_vp, c_i32, c_i32]
+    lib.tvolap_select_ir.argtypes = [c_vp, c_vp]
+    lib.tvolap_process_block.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp]
+    lib.tvolap_reset.argtypes = [c_vp]
+    lib.tvolap_get_info.argtypes = [c_vp, ctypes.POINTER(TvolapInfo)]
+    lib.tvolap_get_partitions.argtypes = [c_vp, c_vp]
+    lib.tvolap_set_timing.argtypes = [c_vp, c_i32]
+    lib.tvolap_get_timing.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i64)]
+    lib.tvolap_last_error.argtypes = [c_vp]
+    lib.tvolap_last_error.restype = ctypes.c_char_p
+    lib.tvolap_version.argtypes = []
+    lib.tvolap_version.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        fn = getattr(lib, name)
+        if fn.restype is None or fn.restype is ctypes.c_int:
+            if name not in ("tvolap_last_error", "tvolap_version"):
+                fn.restype = c_int
+
+
+def load():
+    """Load libtvolap.so (once). Raises if it is missing or if loading it
+    would put a second HIP runtime into the process."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2310_00319_amd.build` "
+            "(there is no CPU fallback)")
+    before = _hip_runtimes_mapped()
+    lib = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_LOCAL)
+    after = _hip_runtimes_mapped()
+    if len(after) > 1:
+        raise RuntimeError(f"two HIP runtimes are mapped into the process: {after} (was {before})")
+    _declare(lib)
+    _lib = lib
+    return lib
+
+
+def check(code: int, handle=None):
+    if code != TVOLAP_OK:
+        msg = load().tvolap_last_error(handle).decode(errors="replace")
+        raise TvolapError(code, msg)

@@ -1,0 +1,70 @@
+"""Helpers shared by the GPU parity tests: run a synthetic workload through the
+HIP library and through the FP64 oracle, and compare per channel."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle as orc
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_rms_per_channel(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    num = np.sqrt(np.sum((got - ref) ** 2, axis=-1))
+    den = np.sqrt(np.sum(ref ** 2, axis=-1))
+    return num / np.maximum(den, 1e-300)
+
+
+def oracle_streams(wl, channels=None, dtype: str = "f32") -> np.ndarray:
+    """FP64 oracle stream outputs [len(channels)][n_calls*L] of a workload.
+    dtype "f32" = exact oracle; "bf16"/"f16" = spectra rounded before the MAC."""
+    chans = list(range(wl.n_channels)) if channels is None else list(channels)
+    L = wl.hop
+    x = wl.padded_input().astype(np.float64)
+    out = np.zeros((len(chans), wl.n_calls * L))
+    for j, c in enumerate(chans):
+        H = orc.channel_spectra([t.astype(np.float64) for t in wl.taps[c]], L, int(wl.taps_of_channel[c]))
+        xin = x[int(wl.input_of_channel[c])]
+        if dtype == "f32":
+            out[j] = orc.tvolap_stream(xin, H, wl.schedule[:, c], L, wl.n_calls)
+        else:
+            out[j] = orc.quantized_tvolap_streams(xin[None, :], [0], [H], wl.schedule[:, [c]], L,
+                                                  wl.n_calls, dtype)[0]
+    return out
+
+
+def make_convolver(wl, dtype: str = "f32", stream=None):
+    from paper_2310_00319_amd import Convolver
+
+    conv = Convolver(hop=wl.hop, n_channels=wl.n_channels, max_taps=wl.max_taps(),
+                     n_inputs=wl.n_inputs, input_of_channel=wl.input_of_channel,
+                     taps_of_channel=wl.taps_of_channel, n_slots=wl.n_slots, dtype=dtype, stream=stream)
+    for c in range(wl.n_channels):
+        for s in range(wl.n_slots):
+            conv.set_ir(c, s, wl.taps[c][s])
+    return conv
+
+
+def gpu_streams(wl, dtype: str = "f32", conv=None):
+    """Whole workload through the library with a device-resident schedule.
+    Returns the [C][n_calls*L] output as float64 numpy."""
+    import torch
+
+    own = conv is None
+    if own:
+        conv = make_convolver(wl, dtype)
+    x = torch.from_numpy(wl.padded_input()).cuda()
+    sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
+    out = conv.process(x, sched)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().astype(np.float64)
+    if own:
+        conv.close()
+    return res

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: FP32 storage within 1e-5 relative RMS per channel (the whole emitted
+stream of the channel). Reduced-precision storage: within 2e-4 relative RMS of
+the oracle with the same spectra rounded (the GPU rounds FP32 transforms, the
+oracle FP64 ones, so an element near a rounding boundary can land one unit of
+the 8-bit (bf16) or 11-bit (f16) significand apart), and an SNR against the
+exact oracle above the bound that the storage precision allows.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import gpu_streams, log, make_convolver, oracle_streams, rel_rms_per_channel
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2310_00319_amd as pkg
+    pkg.load()
+    yield
+
+
+def _check(wl, dtype="f32", channels=None, tol=TOL_F32, name=""):
+    got = gpu_streams(wl, dtype)
+    chans = list(range(wl.n_channels)) if channels is None else list(channels)
+    ref = oracle_streams(wl, chans)
+    err = rel_rms_per_channel(got[chans], ref)
+    log(f"{name}: max rel-RMS {err.max():.3e} over {len(chans)} channels")
+    assert np.all(np.isfinite(got))
+    assert err.max() <= tol, (name, err.max(), int(np.argmax(err)))
+    return got, ref
+
+
+# ------------------------------------------------------------------ small, exhaustive
+
+@pytest.mark.parametrize("L", [64, 128, 256, 512])
+def test_delta_ir_returns_input_delayed_by_hop(L):
+    log(f"delta L={L}")
+    wl = synth.random_small(seed=L, hop=L, n_channels=3, n_inputs=3, n_samples=L * 9 + 17,
+                            taps_range=(1, 1), n_slots=1, p_switch=0.0)
+    for c in range(3):
+        wl.taps[c][0] = np.array([1.0], np.float32)
+    got = gpu_streams(wl)
+    x = wl.padded_input()
+    n = wl.n_calls * L
+    assert np.max(np.abs(got[:, :L])) < 1e-6
+    assert np.max(np.abs(got[:, L:n] - x[:, : n - L])) < 2e-6
+
+
+SMALL_CASES = [
+    # seed, L, C, I, N, taps range, K, p_switch
+    (1, 64, 4, 4, 64 * 40 + 5, (1, 2000), 2, 0.3),
+    (2, 128, 6, 3, 128 * 30 + 77, (300, 5000), 3, 0.5),
+    (3, 256, 5, 2, 256 * 25 + 1, (512, 6000), 2, 1.0),
+    (4, 512, 3, 3, 512 * 16, (1024, 9000), 2, 0.2),
+    (5, 64, 13, 4, 64 * 50, (50, 3000), 4, 0.4),      # fan-out 4, ragged M
+    (6, 128, 9, 3, 128 * 33, (128, 129), 2, 0.7),      # IR one tap longer than a partition
+    (7, 256, 2, 1, 256 * 12 + 3, (4096, 4096), 2, 0.0),
+]
+
+
+@pytest.mark.parametrize("case", SMALL_CASES, ids=[f"s{c[0]}_L{c[1]}" for c in SMALL_CASES])
+def test_stream_parity_small(case):
+    seed, L, C, I, N, tr, K, p = case
+    log(f"small case {case}")
+    wl = synth.random_small(seed=seed, hop=L, n_channels=C, n_inputs=I, n_samples=N,
+                            taps_range=tr, n_slots=K, p_switch=p)
+    _check(wl, name=f"small{seed}")
+
+
+@pytest.mark.parametrize("dtype,min_snr_db", [("bf16", 40.0), ("f16", 58.0)])
+def test_reduced_precision_storage(dtype, min_snr_db):
+    log(f"reduced precision {dtype}")
+    wl = synth.random_small(seed=11, hop=128, n_channels=6, n_inputs=3, n_samples=128 * 40,
+                            taps_range=(2000, 6000), n_slots=2, p_switch=0.5)
+    got = gpu_streams(wl, dtype)
+    q = oracle_streams(wl, dtype=dtype)
+    exact = oracle_streams(wl)
+    err_q = rel_rms_per_channel(got, q)
+    snr = -20 * np.log10(rel_rms_per_channel(got, exact))
+    log(f"{dtype}: rel-RMS vs rounded oracle max {err_q.max():.3e}; SNR vs exact "
+        f"min {snr.min():.1f} median {np.median(snr):.1f} max {snr.max():.1f} dB")
+    assert err_q.max() <= 2e-4
+    assert snr.min() >= min_snr_db
+
+
+# ------------------------------------------------------------------ API behaviour
+
+def test_host_selection_equals_device_schedule():
+    import torch
+    log("host select vs device schedule")
+    wl = synth.random_small(seed=21, hop=64, n_channels=5, n_inputs=5, n_samples=64 * 30,
+                            taps_range=(100, 1500), n_slots=3, p_switch=0.5)
+    dev = gpu_streams(wl)
+    conv = make_convolver(wl)
+    x = torch.from_numpy(wl.padded_input()).cuda()
+    out = torch.empty((wl.n_channels, wl.n_calls * wl.hop), device="cuda")
+    L = wl.hop
+    for c in range(wl.n_calls):
+        conv.select_ir(wl.schedule[c])
+        conv.process_block(x[:, c * L:(c + 1) * L], out[:, c * L:(c + 1) * L])
+    torch.cuda.synchronize()
+    host = out.cpu().numpy()
+    conv.close()
+    assert np.array_equal(host, dev.astype(np.float32))
+
+
+def test_bitwise_deterministic_and_reset():
+    import torch
+    log("determinism and reset")
+    wl = synth.random_small(seed=22, hop=128, n_channels=4, n_inputs=2, n_samples=128 * 24,
+                            taps_range=(500, 3000), n_slots=2, p_switch=0.3)
+    conv = make_convolver(wl)
+    x = torch.from_numpy(wl.padded_input()).cuda()
+    sched = torch.from_numpy(wl.schedule.astype(np.int32)).cuda()
+    a = conv.process(x, sched).cpu().numpy()
+    conv.reset()
+    b = conv.process(x, sched).cpu().numpy()
+    conv.close()
+    c = gpu_streams(wl)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c.astype(np.float32))
+
+
+def test_set_ir_into_active_slot_takes_effect_next_block():
+    import torch
+    import oracle as orc
+    log("set_ir mid stream")
+    wl = synth.random_small(seed=23, hop=64, n_channels=2, n_inputs=2, n_samples=64 * 30,
+                            taps_range=(300, 700), n_slots=1, p_switch=0.0)
+    new_taps = [synth.decaying_ir(int(wl.taps_of_channel[c]), synth.rng(77, 1, c), 48000, rt60=0.05)
+                .astype(np.float32) for c in range(2)]
+    conv = make_convolver(wl)
+    L = wl.hop
+    x = torch.from_numpy(wl.padded_input()).cuda()
+    out = torch.empty((2, wl.n_calls * L), device="cuda")
+    switch_call = 11
+    for c in range(wl.n_calls):
+        if c == switch_call:
+            for ch in range(2):
+                conv.set_ir(ch, 0, new_taps[ch])
+        conv.process_block(x[:, c * L:(c + 1) * L], out[:, c * L:(c + 1) * L])
+    got = out.cpu().numpy().astype(np.float64)
+    conv.close()
+    xs = wl.padded_input().astype(np.float64)
+    for ch in range(2):
+        H = orc.channel_spectra([wl.taps[ch][0].astype(float), new_taps[ch].astype(float)], L,
+                                int(wl.taps_of_channel[ch]))
+        sched = np.array([0 if c < switch_call else 1 for c in range(wl.n_calls)])
+        ref = orc.tvolap_stream(xs[ch], H, sched, L, wl.n_calls)
+        assert rel_rms_per_channel(got[ch], ref) <= TOL_F32
+
+
+def test_strided_io_zero_and_short_irs_and_slot_clamp():
+    import torch
+    import oracle as orc
+    log("strides, zero IR, short IR, clamp")
+    L = 128
+    wl = synth.random_small(seed=24, hop=L, n_channels=3, n_inputs=3, n_samples=L * 20,
+                            taps_range=(1000, 1000), n_slots=2, p_switch=0.0)
+    conv = make_convolver(wl)
+    conv.set_ir(1, 0, np.zeros(0, np.float32))          # zero IR
+    short = wl.taps[2][0][:37].copy()
+    conv.set_ir(2, 0, short)                             # shorter than the channel's length
+    n = wl.n_calls * L
+    xbig = torch.zeros((3, n + 50), device="cuda")
+    xbig[:, :n] = torch.from_numpy(wl.padded_input()).cuda()
+    obig = torch.full((3, n + 70), 7.0, device="cuda")
+    sched = torch.zeros((wl.n_calls, 3), dtype=torch.int32, device="cuda")
+    sched[:, 0] = -5                                     # clamps to slot 0
+    for c in range(wl.n_calls):
+        conv.process_block(xbig[:, c * L:], obig[:, c * L:], sched[c])
+    got = obig.cpu().numpy().astype(np.float64)
+    conv.close()
+    assert np.all(got[:, n:] == 7.0)                     # nothing written past the stream
+    xs = wl.padded_input().astype(np.float64)
+    assert np.max(np.abs(got[1, :n])) == 0.0
+    for ch, taps in ((0, wl.taps[0][0]), (2, short)):
+        H = orc.channel_spectra([taps.astype(float)], L, int(wl.taps_of_channel[ch]))
+        ref = orc.tvolap_stream(xs[ch], H, np.zeros(wl.n_calls, int), L, wl.n_calls)
+        assert rel_rms_per_channel(got[ch, :n], ref) <= TOL_F32
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def test_full_plain_workload():
+    log("full plain: 1 channel, L=128, 480000 samples, 4096 taps, switch every 50 blocks")
+    wl = synth.plain()
+    _check(wl, name="plain-full")
+
+
+def test_full_binaural_workload_sampled_channels():
+    log("full binaural: 128 channels, L=256, 240000 samples, 96000 taps, 4 slots")
+    wl = synth.binaural()
+    _check(wl, channels=[0, 1, 62, 63, 126, 127], name="binaural-full")
+
+
+def test_full_uneven_workload_sampled_channels():
+    log("full uneven: 512 channels, L=128, 96000 samples, 4800..192000 taps")
+    wl = synth.uneven()
+    lens = wl.taps_of_channel
+    chans = sorted({int(np.argmax(lens)), int(np.argmin(lens)), 0, 255, 511})
+    _check(wl, channels=chans, name="uneven-full")
