@@ -77,6 +77,13 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--mode", default="fused", choices=["fused", "two", "plain"],
+                    help="fused: one kernel per block; two: transform-in + MAC, then transform-out; "
+                         "plain: transform-in, MAC, transform-out kernels")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); channels are independent, "
@@ -104,6 +111,14 @@ def main():
             conv.set_ir(c, s, wl.taps[c][s])
     torch.cuda.synchronize()
     t_setir = time.perf_counter() - t0
+    tuned_us = None
+    if args.mode != "fused" or args.chunk or args.waves or args.grid or args.no_autotune:
+        conv.configure(fused={"fused": 1, "two": 2, "plain": 0}[args.mode], chunk=args.chunk, waves=args.waves,
+                       grid=args.grid)
+    else:
+        t0 = time.perf_counter()
+        tuned_us = conv.autotune(iters=10)
+        log(f"autotuned in {time.perf_counter() - t0:.2f} s: best {tuned_us:.2f} us/block")
     info = conv.info()
     log(f"IR bank loaded in {t_setir:.2f} s; info {info}")
 
@@ -140,11 +155,20 @@ def main():
     roof = None
     if timing and timing["blocks"] > 0:
         mac_ms = timing["ms_mac"] / timing["blocks"]
-        achieved = info["mac_bytes_per_block"] / (mac_ms * 1e-3) / 1e9
+        if info["fused"] == 1:
+            kbytes = info["block_bytes"]
+            kname = "k_block (fused: transform-in, spectral MAC of eq. 8, transform-out + overlap-add)"
+        elif info["fused"] == 2:
+            kbytes = info["mac_bytes_per_block"]
+            kname = "k_block (transform-in fused into the spectral MAC of eq. 8)"
+        else:
+            kbytes = info["mac_bytes_per_block"]
+            kname = "k_mac (spectral MAC of eq. 8)"
+        achieved = kbytes / (mac_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_mac (spectral MAC, eq. 8)",
-                "bytes_per_launch": info["mac_bytes_per_block"],
+                "kernel": kname,
+                "bytes_per_launch": kbytes,
                 "avg_launch_us": round(mac_ms * 1e3, 3),
                 "phase_us_per_block": {"in": round(1e3 * timing["ms_in"] / timing["blocks"], 3),
                                        "mac": round(1e3 * mac_ms, 3),
@@ -177,6 +201,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "ir_bank_load_s": round(t_setir, 3),
+        "schedule": {"mode": {1: "fused", 2: "two", 0: "plain"}[info["fused"]], "chunk": info["mac_chunk"],
+                     "waves": info["mac_waves"], "grid": info["mac_grid"], "work_items": info["n_work_items"],
+                     "autotuned_us_per_block": tuned_us},
     }
     conv.close()
     print(json.dumps(res), flush=True)

@@ -82,7 +82,9 @@ typedef struct {
   int32_t n_work_items;             /* MAC work items per block                          */
   int32_t mac_chunk;                /* partitions per MAC work item                      */
   int32_t mac_waves;                /* waves per MAC workgroup                           */
-  int32_t mac_grid;                 /* MAC workgroups launched (persistent grid size)    */
+  int32_t mac_grid;                 /* MAC workgroups launched (each loops over items)   */
+  int32_t fused;                    /* launches per block: 1 -> one, 2 -> two, 0 -> three */
+  int32_t n_cu;                     /* compute units of the device                       */
 } tvolap_info;
 
 /* Create a convolver (Sec. 2: partitioned, block-synchronously switchable,
@@ -143,6 +145,39 @@ int tvolap_get_info(const tvolap_t* h, tvolap_info* info);
 
 /* Partition count M_c of every channel into the host array m_of_channel [C]. */
 int tvolap_get_partitions(const tvolap_t* h, int32_t* m_of_channel);
+
+/* Scheduling of the per-block work (no effect on results beyond the order of
+ * floating-point additions). fused == 1: one kernel launch per block in which
+ * the work items holding partition 0 also transform the new input block and
+ * the last item to finish a channel transforms back and overlap-adds;
+ * fused == 2: two launches (transform-in fused into the spectral MAC, then
+ * transform-out); fused == 0: three launches (transform-in, spectral MAC,
+ * transform-out). chunk:
+ * partitions per work item (0 = about four items per compute unit). waves: 4
+ * or 8 waves per workgroup splitting a work item's partitions (0 = 4). grid:
+ * workgroups launched, each looping over the work items (0 = one per item).
+ * Waits for the stream; rebuilds the work list. Errors: EINVAL, ESTATE during
+ * capture, ENOMEM/EDEVICE. */
+int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, int32_t grid);
+
+/* Autotuner for the fused schedules: times `iters` blocks (zero input, current
+ * bank and selection) for each candidate (fused 1 or 2, chunk, waves, grid),
+ * keeps the
+ * fastest, caches it for handles of the same shape in this process, and then
+ * resets the stream state as tvolap_reset does. *best_us (may be NULL)
+ * receives the best time per block in microseconds, or -1 when the choice came
+ * from the cache. Synchronous. Errors: EINVAL, ESTATE during capture, EDEVICE. */
+int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us);
+
+/* HIP graph capture of the handle's stream (which must not be the null
+ * stream). Device work enqueued between begin and end (process_block with
+ * device slot arrays, set_ir with device taps, reset) is recorded instead of
+ * executed; select_ir and host taps are refused with ESTATE during capture.
+ * tvolap_graph_launch replays the recording on the stream; the block counter
+ * lives in device memory, so every replay continues the stream. */
+int tvolap_capture_begin(tvolap_t* h);
+int tvolap_capture_end(tvolap_t* h);
+int tvolap_graph_launch(tvolap_t* h);
 
 /* Kernel timing. With enable != 0, every processed block records HIP events
  * on the handle's stream around its kernels. tvolap_get_timing waits for the

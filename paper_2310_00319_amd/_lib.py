@@ -29,6 +29,8 @@ EXPORTED = (
     "tvolap_create", "tvolap_destroy", "tvolap_set_ir", "tvolap_select_ir",
     "tvolap_process_block", "tvolap_reset", "tvolap_get_info", "tvolap_get_partitions",
     "tvolap_set_timing", "tvolap_get_timing", "tvolap_last_error", "tvolap_version",
+    "tvolap_configure", "tvolap_autotune", "tvolap_capture_begin", "tvolap_capture_end",
+    "tvolap_graph_launch",
 )
 
 
@@ -62,6 +64,8 @@ class TvolapInfo(ctypes.Structure):
         ("mac_chunk", ctypes.c_int32),
         ("mac_waves", ctypes.c_int32),
         ("mac_grid", ctypes.c_int32),
+        ("fused", ctypes.c_int32),
+        ("n_cu", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -105,6 +109,11 @@ def _declare(lib):
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_i64)]
     lib.tvolap_last_error.argtypes = [c_vp]
     lib.tvolap_last_error.restype = ctypes.c_char_p
+    lib.tvolap_configure.argtypes = [c_vp, c_i32, c_i32, c_i32, c_i32]
+    lib.tvolap_autotune.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_float)]
+    lib.tvolap_capture_begin.argtypes = [c_vp]
+    lib.tvolap_capture_end.argtypes = [c_vp]
+    lib.tvolap_graph_launch.argtypes = [c_vp]
     lib.tvolap_version.argtypes = []
     lib.tvolap_version.restype = ctypes.c_char_p
     for name in EXPORTED:

@@ -159,6 +159,24 @@ class Convolver:
                 check(rc, h)
         return out
 
+    def configure(self, fused=1, chunk: int = 0, waves: int = 0, grid: int = 0):
+        """fused: 1 = one launch per block, 2 = two launches, 0 (or False) = three."""
+        check(self._lib.tvolap_configure(self._h, int(fused), int(chunk), int(waves), int(grid)), self._h)
+
+    def autotune(self, iters: int = 20) -> float:
+        best = ctypes.c_float()
+        check(self._lib.tvolap_autotune(self._h, int(iters), ctypes.byref(best)), self._h)
+        return best.value
+
+    def capture_begin(self):
+        check(self._lib.tvolap_capture_begin(self._h), self._h)
+
+    def capture_end(self):
+        check(self._lib.tvolap_capture_end(self._h), self._h)
+
+    def graph_launch(self):
+        check(self._lib.tvolap_graph_launch(self._h), self._h)
+
     def reset(self):
         check(self._lib.tvolap_reset(self._h), self._h)
 

@@ -1,11 +1,13 @@
 // Host runtime behind include/tvolap.h: validation, plan construction, device
-// buffers and the per-block launch sequence.
+// buffers, the per-block launch sequence, the MAC autotuner and graph capture.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -13,6 +15,7 @@
 #include "../../include/tvolap.h"
 #include "tvolap_internal.h"
 
+using tvx::BlockArgs;
 using tvx::DevPlan;
 using tvx::MacShape;
 using tvx::WorkItem;
@@ -22,11 +25,25 @@ namespace {
 thread_local std::string g_create_error = "no error";
 
 constexpr int kTimingRing = 64;
+constexpr int kSelRing = 16;
 
 struct TimingSet {
   hipEvent_t ev[4];
   bool pending = false;
+  int mode = 0;   // launch mode of the recorded block (see MacChoice::fused)
 };
+
+// fused: 0 = three launches per block (transform-in, MAC, transform-out);
+// 1 = one launch (the last work item of a channel transforms back);
+// 2 = two launches (transform-in fused into the MAC, then transform-out).
+struct MacChoice {
+  int32_t chunk = 0, waves = 4, grid = 0, fused = 1;
+};
+
+// Autotuner results, keyed by the handle's shape (hop, channels, inputs,
+// dtype, input map and partition counts).
+std::mutex g_tune_mu;
+std::map<std::string, MacChoice> g_tune_cache;
 
 }  // namespace
 
@@ -34,6 +51,7 @@ struct tvolap {
   // configuration
   int32_t L = 0, C = 0, I = 0, K = 0, dtype = 0, max_taps = 0;
   int device = 0;
+  int n_cu = 256;
   hipStream_t stream = nullptr;
   std::vector<int32_t> ch_input, ch_taps, ch_M, in_M;
   std::vector<int64_t> ch_bank_off, in_fdl_off;
@@ -55,25 +73,40 @@ struct tvolap {
   int32_t* d_in_M = nullptr;
   int64_t* d_in_fdl_off = nullptr;
   float* d_taps = nullptr;      // [max_taps] staging for host taps
+  int32_t* d_arrive = nullptr;  // [C]
+  int32_t* d_done = nullptr;    // [1]
+  float* d_zero_in = nullptr;   // [I][L] zeros (autotuner input)
+  float* d_tune_out = nullptr;  // [C][L] autotuner output
+  int32_t* d_tune_sel = nullptr;  // [K][C] autotuner selections (row k: every channel in slot k)
+  int32_t* d_in_ch_ptr = nullptr; // [I+1]
+  int32_t* d_in_ch = nullptr;     // [C]
 
   // MAC work list
   MacShape shape{2, 1, 4};
+  MacChoice choice;
   int32_t tile_width = 128;
   int32_t chunk = 0;
-  std::vector<WorkItem> items;
-  WorkItem* d_items = nullptr;
+  std::vector<WorkItem> items;    // n_spec spectrum items, then n_mac MAC items
+  int32_t n_spec = 0, n_mac = 0;
+  std::vector<int32_t> ch_row_base, ch_nchunks, needed;
   int32_t n_rows = 0;
+  WorkItem* d_items = nullptr;
   float2* d_ypart = nullptr;    // [n_rows][tile_width]
-  int32_t* d_rows_ptr = nullptr;
-  int32_t* d_rows = nullptr;
+  int32_t* d_ch_row_base = nullptr;
+  int32_t* d_ch_nchunks = nullptr;
+  int32_t* d_needed = nullptr;
 
   // pinned staging ring for host slot selections
-  static constexpr int kSelRing = 16;
-  int32_t* h_sel_ring = nullptr;   // [kSelRing][C], hipHostMalloc
+  int32_t* h_sel_ring = nullptr;  // [kSelRing][C], hipHostMalloc
   hipEvent_t sel_ev[kSelRing];
   bool sel_ev_used[kSelRing] = {};
   bool sel_ev_made = false;
   int sel_next = 0;
+
+  // graph capture
+  bool capturing = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 
   // timing
   bool timing = false;
@@ -84,11 +117,14 @@ struct tvolap {
   bool events_made = false;
 
   std::string err = "no error";
+
   DevPlan plan() const {
     DevPlan P;
     P.L = L; P.C = C; P.I = I; P.K = K;
     P.ch_input = d_ch_input; P.ch_M = d_ch_M; P.ch_bank_off = d_ch_bank_off;
     P.in_M = d_in_M; P.in_fdl_off = d_in_fdl_off; P.tw = d_tw; P.win = d_win;
+    P.ch_row_base = d_ch_row_base; P.ch_nchunks = d_ch_nchunks; P.tile_width = tile_width;
+    P.in_ch_ptr = d_in_ch_ptr; P.in_ch = d_in_ch;
     return P;
   }
 };
@@ -111,6 +147,12 @@ int hip_fail(tvolap_t* h, hipError_t e, const char* what) {
     if (_e != hipSuccess) return hip_fail((h), _e, #expr); \
   } while (0)
 
+#define RC_TRY(expr)                  \
+  do {                                \
+    int _rc = (expr);                 \
+    if (_rc != TVOLAP_OK) return _rc; \
+  } while (0)
+
 template <typename T>
 hipError_t dalloc(T** p, size_t bytes) {
   *p = nullptr;
@@ -118,28 +160,52 @@ hipError_t dalloc(T** p, size_t bytes) {
   return hipMalloc(reinterpret_cast<void**>(p), bytes);
 }
 
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_work(tvolap_t* h) {
+  dfree(h->d_items);
+  dfree(h->d_ypart);
+  dfree(h->d_ch_row_base);
+  dfree(h->d_ch_nchunks);
+  dfree(h->d_needed);
+}
+
 void free_all(tvolap_t* h) {
-  void* bufs[] = {h->d_bank, h->d_fdl, h->d_hist, h->d_ola, h->d_sel, h->d_counter, h->d_tw, h->d_win,
-                  h->d_ch_input, h->d_ch_M, h->d_ch_bank_off, h->d_in_M, h->d_in_fdl_off, h->d_taps,
-                  h->d_items, h->d_ypart, h->d_rows_ptr, h->d_rows};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->graph_exec = nullptr;
+  h->graph = nullptr;
+  free_work(h);
+  dfree(h->d_bank); dfree(h->d_fdl); dfree(h->d_hist); dfree(h->d_ola); dfree(h->d_sel);
+  dfree(h->d_counter); dfree(h->d_tw); dfree(h->d_win); dfree(h->d_ch_input); dfree(h->d_ch_M);
+  dfree(h->d_ch_bank_off); dfree(h->d_in_M); dfree(h->d_in_fdl_off); dfree(h->d_taps);
+  dfree(h->d_arrive); dfree(h->d_done); dfree(h->d_zero_in); dfree(h->d_tune_out); dfree(h->d_tune_sel);
+  dfree(h->d_in_ch_ptr); dfree(h->d_in_ch);
   if (h->events_made)
     for (auto& t : h->tsets)
       for (auto& e : t.ev) (void)hipEventDestroy(e);
   if (h->sel_ev_made)
     for (auto& e : h->sel_ev) (void)hipEventDestroy(e);
   if (h->h_sel_ring) (void)hipHostFree(h->h_sel_ring);
+  h->h_sel_ring = nullptr;
 }
 
 bool supported_hop(int L) { return L == 64 || L == 128 || L == 256 || L == 512; }
 
 // Build the MAC work list: channels grouped by input (up to G per item), the
-// 2L bins cut into tiles of 64*V, the partitions into chunks.
-void build_work(tvolap_t* h, int chunk_override) {
+// 2L bins cut into tiles of 64 V, each channel group's partition range cut
+// into chunks of `S` partitions. The partial-spectrum rows of a channel are
+// contiguous in (tile, chunk) order, so the channel's spectrum is the sum over
+// chunks of rows base + tile * nchunks + chunk.
+void build_work(tvolap_t* h, int S_req, int waves) {
   const int N = 2 * h->L;
   const int V = (h->dtype == 0) ? 2 : std::min(4, N / 64);
   h->shape.V = V;
+  h->shape.NW = (waves == 8) ? 8 : 4;
   h->tile_width = 64 * V;
   const int T = N / h->tile_width;
 
@@ -157,74 +223,105 @@ void build_work(tvolap_t* h, int chunk_override) {
     for (size_t j = 0; j < v.size(); j += G) {
       Sub s;
       s.input = i;
-      int Ms = 0;
-      for (size_t k = j; k < std::min(v.size(), j + G); ++k) {
+      s.M = 0;
+      for (size_t k = j; k < std::min(v.size(), j + (size_t)G); ++k) {
         s.ch.push_back(v[k]);
-        Ms = std::max(Ms, h->ch_M[v[k]]);
+        s.M = std::max(s.M, h->ch_M[v[k]]);
       }
-      s.M = Ms;
       subs.push_back(s);
     }
   }
+  // MAC items cover partitions m >= 1; the m = 0 term is added when a channel
+  // is completed, from the spectrum computed in the same block.
   int64_t units = 0;
-  for (auto& s : subs) units += (int64_t)s.M * T;
-  int S = chunk_override;
+  for (auto& s : subs) units += (int64_t)(s.M - 1) * T;
+  int S = S_req;
   if (S <= 0) {
-    // about four workgroups per compute unit of a 256-CU device
-    const int64_t target = 1024;
-    S = (int)std::max<int64_t>(8, (units + target - 1) / target);
+    // about four workgroups per compute unit
+    const int64_t target = 4LL * h->n_cu;
+    S = (int)std::max<int64_t>(4, (units + target - 1) / target);
   }
   h->chunk = S;
 
-  struct Tmp { WorkItem w; int size; };
-  std::vector<Tmp> tmp;
-  for (auto& s : subs)
-    for (int t = 0; t < T; ++t)
-      for (int m0 = 0; m0 < s.M; m0 += S) {
-        WorkItem w{};
-        w.input = s.input;
-        w.n_ch = (int)s.ch.size();
-        w.m0 = m0;
-        w.m1 = std::min(s.M, m0 + S);
-        w.tile = t;
-        for (int g = 0; g < 4; ++g) w.ch[g] = g < w.n_ch ? s.ch[g] : 0;
-        tmp.push_back({w, w.m1 - w.m0});
-      }
-  // largest items first so that the tail of the launch is made of small ones
-  std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.size > b.size; });
-  h->items.clear();
+  h->ch_row_base.assign(h->C, 0);
+  h->ch_nchunks.assign(h->C, 0);
+  h->needed.assign(h->C, 0);
   int row = 0;
-  for (auto& t : tmp) {
-    t.w.row = row;
-    row += t.w.n_ch;
-    h->items.push_back(t.w);
+  for (auto& s : subs) {
+    const int nch = (s.M - 1 + S - 1) / S;
+    for (int c : s.ch) {
+      h->ch_row_base[c] = row;
+      h->ch_nchunks[c] = nch;
+      h->needed[c] = nch * T + 1;   // MAC items + the input's spectrum item
+      row += nch * T;
+    }
   }
   h->n_rows = row;
+
+  struct Tmp { WorkItem w; int size; };
+  std::vector<Tmp> tmp;
+  for (auto& s : subs) {
+    const int nch = (s.M - 1 + S - 1) / S;
+    for (int t = 0; t < T; ++t)
+      for (int j = 0; j < nch; ++j) {
+        WorkItem w{};
+        w.kind = 0;
+        w.input = s.input;
+        w.n_ch = (int)s.ch.size();
+        w.m0 = 1 + j * S;
+        w.m1 = std::min(s.M, 1 + (j + 1) * S);
+        w.tile = t;
+        w.chunk = j;
+        for (int g = 0; g < 4; ++g) {
+          const int c = g < w.n_ch ? s.ch[g] : s.ch[0];
+          w.ch[g] = c;
+          w.row[g] = h->ch_row_base[c] + t * nch + j;
+        }
+        tmp.push_back({w, w.m1 - w.m0});
+      }
+  }
+  // largest items first, so that the launch ends with small ones
+  std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.size > b.size; });
+  h->items.clear();
+  for (int i = 0; i < h->I; ++i) {
+    WorkItem w{};
+    w.kind = 1;
+    w.input = i;
+    h->items.push_back(w);
+  }
+  for (auto& t : tmp) h->items.push_back(t.w);
+  h->n_spec = h->I;
+  h->n_mac = (int32_t)tmp.size();
 }
 
 int upload_work(tvolap_t* h) {
-  const int N = 2 * h->L;
-  const int T = N / h->tile_width;
-  // rows of every (channel, tile) in item order
-  std::vector<std::vector<int32_t>> lists((size_t)h->C * T);
-  for (auto& w : h->items)
-    for (int g = 0; g < w.n_ch; ++g) lists[(size_t)w.ch[g] * T + w.tile].push_back(w.row + g);
-  std::vector<int32_t> ptr((size_t)h->C * T + 1, 0), rows;
-  for (size_t k = 0; k < lists.size(); ++k) {
-    // sum partial spectra in increasing partition order (fixed, deterministic)
-    std::sort(lists[k].begin(), lists[k].end(), [&](int32_t a, int32_t b) { return a < b; });
-    ptr[k + 1] = ptr[k] + (int32_t)lists[k].size();
-    rows.insert(rows.end(), lists[k].begin(), lists[k].end());
-  }
+  free_work(h);
   HIP_TRY(h, dalloc(&h->d_items, h->items.size() * sizeof(WorkItem)));
   HIP_TRY(h, dalloc(&h->d_ypart, (size_t)h->n_rows * h->tile_width * sizeof(float2)));
-  HIP_TRY(h, dalloc(&h->d_rows_ptr, ptr.size() * sizeof(int32_t)));
-  HIP_TRY(h, dalloc(&h->d_rows, rows.size() * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_ch_row_base, (size_t)h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_ch_nchunks, (size_t)h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_needed, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, hipMemcpy(h->d_items, h->items.data(), h->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
-  HIP_TRY(h, hipMemcpy(h->d_rows_ptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  if (!rows.empty())
-    HIP_TRY(h, hipMemcpy(h->d_rows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_ch_row_base, h->ch_row_base.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_ch_nchunks, h->ch_nchunks.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_needed, h->needed.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
   return TVOLAP_OK;
+}
+
+int apply_choice(tvolap_t* h, const MacChoice& c) {
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  build_work(h, c.chunk, c.waves);
+  RC_TRY(upload_work(h));
+  h->choice = c;
+  h->choice.chunk = h->chunk;
+  h->choice.waves = h->shape.NW;
+  return TVOLAP_OK;
+}
+
+int grid_of(const tvolap_t* h) {
+  const int n = (int)h->items.size();
+  if (h->choice.grid <= 0 || h->choice.grid > n) return n;
+  return h->choice.grid;
 }
 
 int create_impl(const tvolap_config* cfg, tvolap_t* h) {
@@ -237,6 +334,11 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   h->stream = static_cast<hipStream_t>(cfg->stream);
   h->store_bytes = (h->dtype == TVOLAP_F32) ? 8 : 4;
   HIP_TRY(h, hipGetDevice(&h->device));
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cus > 0)
+      h->n_cu = cus;
+  }
   const int L = h->L, N = 2 * L;
 
   h->ch_input.resize(h->C);
@@ -278,6 +380,27 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_in_M, (size_t)h->I * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_in_fdl_off, (size_t)h->I * sizeof(int64_t)));
   HIP_TRY(h, dalloc(&h->d_taps, (size_t)h->max_taps * sizeof(float)));
+  HIP_TRY(h, dalloc(&h->d_arrive, (size_t)h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_done, sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_zero_in, (size_t)h->I * L * sizeof(float)));
+  HIP_TRY(h, dalloc(&h->d_tune_out, (size_t)h->C * L * sizeof(float)));
+  HIP_TRY(h, dalloc(&h->d_tune_sel, (size_t)h->K * h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_in_ch_ptr, (size_t)(h->I + 1) * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_in_ch, (size_t)h->C * sizeof(int32_t)));
+  {
+    std::vector<int32_t> ts((size_t)h->K * h->C);
+    for (int k = 0; k < h->K; ++k)
+      for (int c = 0; c < h->C; ++c) ts[(size_t)k * h->C + c] = k;
+    HIP_TRY(h, hipMemcpy(h->d_tune_sel, ts.data(), ts.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    std::vector<int32_t> ptr(h->I + 1, 0), chs;
+    for (int i = 0; i < h->I; ++i) {
+      for (int c = 0; c < h->C; ++c)
+        if (h->ch_input[c] == i) chs.push_back(c);
+      ptr[i + 1] = (int32_t)chs.size();
+    }
+    HIP_TRY(h, hipMemcpy(h->d_in_ch_ptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->d_in_ch, chs.data(), chs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
 
   // twiddles exp(-2 pi i t / 4L) and the Hann window, evaluated in double precision
   std::vector<float2> tw(4 * L);
@@ -301,15 +424,17 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   HIP_TRY(h, hipMemsetAsync(h->d_ola, 0, (size_t)h->C * 3 * L * sizeof(float), h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_sel, 0, (size_t)h->C * sizeof(int32_t), h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_counter, 0, sizeof(uint64_t), h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->d_arrive, 0, (size_t)h->C * sizeof(int32_t), h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->d_done, 0, sizeof(int32_t), h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->d_zero_in, 0, (size_t)h->I * L * sizeof(float), h->stream));
 
-  HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->h_sel_ring),
-                           (size_t)tvolap_t::kSelRing * h->C * sizeof(int32_t), hipHostMallocDefault));
+  HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->h_sel_ring), (size_t)kSelRing * h->C * sizeof(int32_t),
+                           hipHostMallocDefault));
   for (auto& e : h->sel_ev) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   h->sel_ev_made = true;
 
-  build_work(h, 0);
-  int rc = upload_work(h);
-  if (rc != TVOLAP_OK) return rc;
+  MacChoice c;
+  RC_TRY(apply_choice(h, c));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   return TVOLAP_OK;
 }
@@ -318,9 +443,16 @@ void drain_timing(tvolap_t* h, TimingSet& t) {
   if (!t.pending) return;
   float a = 0, b = 0, c = 0;
   if (hipEventSynchronize(t.ev[3]) == hipSuccess) {
-    (void)hipEventElapsedTime(&a, t.ev[0], t.ev[1]);
-    (void)hipEventElapsedTime(&b, t.ev[1], t.ev[2]);
-    (void)hipEventElapsedTime(&c, t.ev[2], t.ev[3]);
+    if (t.mode == 1) {
+      (void)hipEventElapsedTime(&b, t.ev[0], t.ev[3]);
+    } else if (t.mode == 2) {
+      (void)hipEventElapsedTime(&b, t.ev[0], t.ev[2]);
+      (void)hipEventElapsedTime(&c, t.ev[2], t.ev[3]);
+    } else {
+      (void)hipEventElapsedTime(&a, t.ev[0], t.ev[1]);
+      (void)hipEventElapsedTime(&b, t.ev[1], t.ev[2]);
+      (void)hipEventElapsedTime(&c, t.ev[2], t.ev[3]);
+    }
     h->ms_in += a;
     h->ms_mac += b;
     h->ms_out += c;
@@ -329,11 +461,96 @@ void drain_timing(tvolap_t* h, TimingSet& t) {
   t.pending = false;
 }
 
+// Enqueue one block. Timing events are recorded only outside graph capture.
+// sel_dev: this block's slots (device) or NULL for the handle's selection;
+// copy_sel: make sel_dev the handle's selection.
+int enqueue_block(tvolap_t* h, const float* in, int64_t in_stride, float* out, int64_t out_stride,
+                  const int32_t* sel_dev, bool copy_sel) {
+  const DevPlan P = h->plan();
+  const int32_t* sel = sel_dev ? sel_dev : h->d_sel;
+  TimingSet* ts = nullptr;
+  if (h->timing && !h->capturing) {
+    ts = &h->tsets[h->tnext];
+    h->tnext = (h->tnext + 1) % kTimingRing;
+    drain_timing(h, *ts);
+    ts->mode = h->choice.fused;
+  }
+  if (h->choice.fused) {
+    BlockArgs A;
+    A.P = P;
+    A.items = h->d_items;
+    A.n_items = (int32_t)h->items.size();
+    A.bank = h->d_bank;
+    A.fdl = h->d_fdl;
+    A.sel = sel;
+    A.sel_store = h->d_sel;
+    A.copy_sel = copy_sel ? 1 : 0;
+    A.in = in;
+    A.in_stride = in_stride;
+    A.hist = h->d_hist;
+    A.ypart = h->d_ypart;
+    A.arrive = h->d_arrive;
+    A.needed = h->d_needed;
+    A.done = h->d_done;
+    A.ola = h->d_ola;
+    A.out = out;
+    A.out_stride = out_stride;
+    A.counter = h->d_counter;
+    A.inverse_inline = h->choice.fused == 1 ? 1 : 0;
+    if (ts) HIP_TRY(h, hipEventRecord(ts->ev[0], h->stream));
+    HIP_TRY(h, tvx::launch_block(A, h->dtype, h->shape, grid_of(h), h->stream));
+    if (h->choice.fused == 2) {
+      if (ts) HIP_TRY(h, hipEventRecord(ts->ev[2], h->stream));
+      HIP_TRY(h, tvx::launch_inv(P, h->dtype, h->d_ypart, h->d_bank, h->d_fdl, sel, h->d_ola, out, out_stride,
+                                 copy_sel ? 1 : 0, h->d_sel, h->d_done, h->d_counter, h->stream));
+    }
+    if (ts) {
+      HIP_TRY(h, hipEventRecord(ts->ev[3], h->stream));
+      ts->pending = true;
+    }
+    return TVOLAP_OK;
+  }
+  if (ts) HIP_TRY(h, hipEventRecord(ts->ev[0], h->stream));
+  HIP_TRY(h, tvx::launch_fwd(P, h->dtype, in, in_stride, h->d_hist, h->d_fdl, h->d_counter, h->stream));
+  if (ts) HIP_TRY(h, hipEventRecord(ts->ev[1], h->stream));
+  HIP_TRY(h, tvx::launch_mac(P, h->dtype, h->shape, h->d_items + h->n_spec, h->n_mac, h->d_bank, h->d_fdl, sel,
+                             h->d_ypart, h->d_counter, h->stream));
+  if (ts) HIP_TRY(h, hipEventRecord(ts->ev[2], h->stream));
+  HIP_TRY(h, tvx::launch_inv(P, h->dtype, h->d_ypart, h->d_bank, h->d_fdl, sel, h->d_ola, out, out_stride,
+                             copy_sel ? 1 : 0, h->d_sel, h->d_done, h->d_counter, h->stream));
+  if (ts) {
+    HIP_TRY(h, hipEventRecord(ts->ev[3], h->stream));
+    ts->pending = true;
+  }
+  return TVOLAP_OK;
+}
+
+int reset_state(tvolap_t* h) {
+  HIP_TRY(h, tvx::launch_fill_zero(h->d_fdl, (size_t)h->fdl_elems * h->store_bytes, h->stream));
+  HIP_TRY(h, tvx::launch_fill_zero(h->d_hist, (size_t)2 * h->I * h->L * sizeof(float), h->stream));
+  HIP_TRY(h, tvx::launch_fill_zero(h->d_ola, (size_t)h->C * 3 * h->L * sizeof(float), h->stream));
+  HIP_TRY(h, tvx::launch_fill_zero(h->d_counter, sizeof(uint64_t), h->stream));
+  HIP_TRY(h, tvx::launch_fill_zero(h->d_arrive, (size_t)h->C * sizeof(int32_t), h->stream));
+  HIP_TRY(h, tvx::launch_fill_zero(h->d_done, sizeof(int32_t), h->stream));
+  return TVOLAP_OK;
+}
+
+std::string tune_key(const tvolap_t* h) {
+  std::string k = std::to_string(h->L) + "/" + std::to_string(h->C) + "/" + std::to_string(h->I) + "/" +
+                  std::to_string(h->dtype) + "/" + std::to_string(h->n_cu) + ":";
+  uint64_t hash = 1469598103934665603ull;
+  for (int c = 0; c < h->C; ++c) {
+    hash = (hash ^ (uint64_t)h->ch_M[c]) * 1099511628211ull;
+    hash = (hash ^ (uint64_t)h->ch_input[c]) * 1099511628211ull;
+  }
+  return k + std::to_string(hash);
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* tvolap_version(void) { return "tvolap-gfx950 0.1"; }
+const char* tvolap_version(void) { return "tvolap-gfx950 0.2"; }
 
 const char* tvolap_last_error(const tvolap_t* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
@@ -357,9 +574,9 @@ int tvolap_create(const tvolap_config* cfg, tvolap_t** out) {
   }
   {
     const int64_t M = (cfg->max_taps + 2LL * cfg->hop - 1) / (2LL * cfg->hop);
-    const int64_t worst = (int64_t)cfg->n_channels * cfg->n_slots * M * 2 * cfg->hop;
-    if (worst > (int64_t)1 << 40) return fail(nullptr, TVOLAP_ENOMEM, "IR bank larger than 2^40 elements");
     if (M > (1 << 24)) return fail(nullptr, TVOLAP_EINVAL, "max_taps too large");
+    const int64_t worst = (int64_t)cfg->n_channels * cfg->n_slots * M * 2 * cfg->hop;
+    if (worst > ((int64_t)1 << 40)) return fail(nullptr, TVOLAP_ENOMEM, "IR bank larger than 2^40 elements");
   }
   tvolap_t* h = new (std::nothrow) tvolap_t();
   if (!h) return fail(nullptr, TVOLAP_ENOMEM, "host allocation failed");
@@ -378,6 +595,11 @@ int tvolap_create(const tvolap_config* cfg, tvolap_t** out) {
 
 int tvolap_destroy(tvolap_t* h) {
   if (!h) return TVOLAP_OK;
+  if (h->capturing) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(h->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+  }
   (void)hipStreamSynchronize(h->stream);
   free_all(h);
   delete h;
@@ -392,6 +614,8 @@ int tvolap_set_ir(tvolap_t* h, int32_t channel, int32_t slot, const float* taps,
   if (n_taps < 0 || n_taps > h->ch_taps[channel])
     return fail(h, TVOLAP_EINVAL, "n_taps outside [0, taps of the channel]");
   if (n_taps > 0 && !taps) return fail(h, TVOLAP_EINVAL, "taps is NULL");
+  if (h->capturing && n_taps > 0 && !taps_on_device)
+    return fail(h, TVOLAP_ESTATE, "host taps cannot be loaded during graph capture");
   const float* src = taps;
   if (n_taps > 0 && !taps_on_device) {
     // Wait for earlier users of the staging buffer, then copy: the host array
@@ -413,6 +637,7 @@ int tvolap_set_ir(tvolap_t* h, int32_t channel, int32_t slot, const float* taps,
 int tvolap_select_ir(tvolap_t* h, const int32_t* slot_of_channel) {
   if (!h) return TVOLAP_EINVAL;
   if (!slot_of_channel) return fail(h, TVOLAP_EINVAL, "slot_of_channel is NULL");
+  if (h->capturing) return fail(h, TVOLAP_ESTATE, "host selections cannot be recorded in a graph");
   for (int c = 0; c < h->C; ++c)
     if (slot_of_channel[c] < 0 || slot_of_channel[c] >= h->K) return fail(h, TVOLAP_EINVAL, "slot out of range");
   // Copy into a pinned ring slot whose previous transfer has completed, then
@@ -424,7 +649,7 @@ int tvolap_select_ir(tvolap_t* h, const int32_t* slot_of_channel) {
   HIP_TRY(h, hipMemcpyAsync(h->d_sel, slot, (size_t)h->C * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(h, hipEventRecord(h->sel_ev[k], h->stream));
   h->sel_ev_used[k] = true;
-  h->sel_next = (k + 1) % tvolap_t::kSelRing;
+  h->sel_next = (k + 1) % kSelRing;
   return TVOLAP_OK;
 }
 
@@ -433,35 +658,153 @@ int tvolap_process_block(tvolap_t* h, const float* in, int64_t in_stride, float*
   if (!h) return TVOLAP_EINVAL;
   if (!in || !out) return fail(h, TVOLAP_EINVAL, "in or out is NULL");
   if (in_stride < h->L || out_stride < h->L) return fail(h, TVOLAP_EINVAL, "stride smaller than hop");
-  const DevPlan P = h->plan();
-  const int32_t* sel = slot_of_channel_dev ? slot_of_channel_dev : h->d_sel;
-  TimingSet* ts = nullptr;
-  if (h->timing) {
-    ts = &h->tsets[h->tnext];
-    h->tnext = (h->tnext + 1) % kTimingRing;
-    drain_timing(h, *ts);
-  }
-  if (ts) HIP_TRY(h, hipEventRecord(ts->ev[0], h->stream));
-  HIP_TRY(h, tvx::launch_fwd(P, h->dtype, in, in_stride, h->d_hist, h->d_fdl, h->d_counter, h->stream));
-  if (ts) HIP_TRY(h, hipEventRecord(ts->ev[1], h->stream));
-  HIP_TRY(h, tvx::launch_mac(P, h->dtype, h->shape, h->d_items, (int)h->items.size(), h->d_bank, h->d_fdl, sel,
-                                h->d_ypart, h->d_counter, h->stream));
-  if (ts) HIP_TRY(h, hipEventRecord(ts->ev[2], h->stream));
-  HIP_TRY(h, tvx::launch_inv(P, h->tile_width, h->d_ypart, h->d_rows_ptr, h->d_rows, h->d_ola, out, out_stride,
-                                slot_of_channel_dev, h->d_sel, h->d_counter, h->stream));
-  if (ts) {
-    HIP_TRY(h, hipEventRecord(ts->ev[3], h->stream));
-    ts->pending = true;
-  }
-  return TVOLAP_OK;
+  return enqueue_block(h, in, in_stride, out, out_stride, slot_of_channel_dev, slot_of_channel_dev != nullptr);
 }
 
 int tvolap_reset(tvolap_t* h) {
   if (!h) return TVOLAP_EINVAL;
-  HIP_TRY(h, tvx::launch_fill_zero(h->d_fdl, (size_t)h->fdl_elems * h->store_bytes, h->stream));
-  HIP_TRY(h, tvx::launch_fill_zero(h->d_hist, (size_t)2 * h->I * h->L * sizeof(float), h->stream));
-  HIP_TRY(h, tvx::launch_fill_zero(h->d_ola, (size_t)h->C * 3 * h->L * sizeof(float), h->stream));
-  HIP_TRY(h, tvx::launch_fill_zero(h->d_counter, sizeof(uint64_t), h->stream));
+  return reset_state(h);
+}
+
+int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, int32_t grid) {
+  if (!h) return TVOLAP_EINVAL;
+  if (h->capturing) return fail(h, TVOLAP_ESTATE, "cannot reconfigure during graph capture");
+  if (chunk < 0 || grid < 0) return fail(h, TVOLAP_EINVAL, "chunk and grid must be >= 0");
+  if (waves != 0 && waves != 4 && waves != 8) return fail(h, TVOLAP_EINVAL, "waves must be 0, 4 or 8");
+  if (fused < 0 || fused > 2) return fail(h, TVOLAP_EINVAL, "fused must be 0, 1 or 2");
+  MacChoice c;
+  c.fused = fused;
+  c.chunk = chunk;
+  c.waves = waves == 0 ? 4 : waves;
+  c.grid = grid;
+  return apply_choice(h, c);
+}
+
+int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us) {
+  if (!h) return TVOLAP_EINVAL;
+  if (h->capturing) return fail(h, TVOLAP_ESTATE, "cannot autotune during graph capture");
+  if (iters < 1) return fail(h, TVOLAP_EINVAL, "iters must be >= 1");
+  const std::string key = tune_key(h);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      RC_TRY(apply_choice(h, it->second));
+      if (best_us) *best_us = -1.f;
+      return reset_state(h);
+    }
+  }
+  // candidate chunk sizes: about 1 to 16 work items per CU
+  const int N = 2 * h->L;
+  const int V = (h->dtype == 0) ? 2 : std::min(4, N / 64);
+  const int T = N / (64 * V);
+  int64_t units = 0;
+  {
+    std::vector<int> maxM(h->I, 0);
+    for (int c = 0; c < h->C; ++c) maxM[h->ch_input[c]] = std::max(maxM[h->ch_input[c]], h->ch_M[c]);
+    for (int i = 0; i < h->I; ++i) units += (int64_t)maxM[i] * T;
+  }
+  std::vector<int> chunks;
+  for (int per_cu : {1, 2, 4, 8, 16}) {
+    const int64_t target = (int64_t)per_cu * h->n_cu;
+    const int S = (int)std::max<int64_t>(2, (units + target - 1) / target);
+    if (std::find(chunks.begin(), chunks.end(), S) == chunks.end()) chunks.push_back(S);
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(h, hipEventCreate(&e0));
+  HIP_TRY(h, hipEventCreate(&e1));
+  const bool timing_was = h->timing;
+  h->timing = false;
+  MacChoice best;
+  float best_t = 1e30f;
+  int rc = TVOLAP_OK;
+  for (int mode : {1, 2})
+  for (int S : chunks) {
+    for (int nw : {4, 8}) {
+      for (int gmul : {0, 1, 2, 4}) {
+        MacChoice c;
+        c.fused = mode;
+        c.chunk = S;
+        c.waves = nw;
+        c.grid = gmul * h->n_cu;
+        rc = apply_choice(h, c);
+        if (rc != TVOLAP_OK) break;
+        if (gmul > 0 && c.grid >= (int)h->items.size()) continue;
+        // every block selects another slot, as a switching stream does, so the
+        // timed traffic is not served from a cache that holds a single slot
+        for (int k = 0; k < 2 && rc == TVOLAP_OK; ++k)
+          rc = enqueue_block(h, h->d_zero_in, h->L, h->d_tune_out, h->L, h->d_tune_sel + (size_t)(k % h->K) * h->C,
+                             false);
+        if (rc != TVOLAP_OK) break;
+        if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = fail(h, TVOLAP_EDEVICE, "event record"); break; }
+        for (int k = 0; k < iters && rc == TVOLAP_OK; ++k)
+          rc = enqueue_block(h, h->d_zero_in, h->L, h->d_tune_out, h->L, h->d_tune_sel + (size_t)(k % h->K) * h->C,
+                             false);
+        if (rc != TVOLAP_OK) break;
+        if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(h, TVOLAP_EDEVICE, "event synchronize");
+          break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const float us = 1e3f * ms / (float)iters;
+        if (us < best_t) {
+          best_t = us;
+          best = h->choice;
+          best.grid = c.grid;
+        }
+      }
+      if (rc != TVOLAP_OK) break;
+    }
+    if (rc != TVOLAP_OK) break;
+  }
+  if (rc == TVOLAP_OK && best_t >= 1e30f) rc = fail(h, TVOLAP_EDEVICE, "autotuner found no candidate");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->timing = timing_was;
+  if (rc != TVOLAP_OK) return rc;
+  RC_TRY(apply_choice(h, best));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  if (best_us) *best_us = best_t;
+  return reset_state(h);
+}
+
+int tvolap_capture_begin(tvolap_t* h) {
+  if (!h) return TVOLAP_EINVAL;
+  if (h->capturing) return fail(h, TVOLAP_ESTATE, "capture already active");
+  if (!h->stream) return fail(h, TVOLAP_ESTATE, "graph capture needs a non-null stream");
+  HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+  h->capturing = true;
+  return TVOLAP_OK;
+}
+
+int tvolap_capture_end(tvolap_t* h) {
+  if (!h) return TVOLAP_EINVAL;
+  if (!h->capturing) return fail(h, TVOLAP_ESTATE, "no capture active");
+  hipGraph_t g = nullptr;
+  h->capturing = false;
+  HIP_TRY(h, hipStreamEndCapture(h->stream, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(h, e, "hipGraphInstantiate");
+  }
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->graph = g;
+  h->graph_exec = ex;
+  return TVOLAP_OK;
+}
+
+int tvolap_graph_launch(tvolap_t* h) {
+  if (!h) return TVOLAP_EINVAL;
+  if (!h->graph_exec) return fail(h, TVOLAP_ESTATE, "no captured graph");
+  if (h->capturing) return fail(h, TVOLAP_ESTATE, "capture active");
+  HIP_TRY(h, hipGraphLaunch(h->graph_exec, h->stream));
   return TVOLAP_OK;
 }
 
@@ -484,15 +827,19 @@ int tvolap_get_info(const tvolap_t* h, tvolap_info* info) {
   // input, the M_i same-parity delay-line spectra (shared by the channels of
   // that input).
   info->mac_bytes_per_block = (sm + si) * N * (int64_t)h->store_bytes;
-  info->block_bytes = info->mac_bytes_per_block + (int64_t)h->I * N * h->store_bytes +
-                      (int64_t)(h->I + h->C) * h->L * 4;
+  info->block_bytes = info->mac_bytes_per_block + (int64_t)h->I * N * h->store_bytes  // new spectra
+                      + (int64_t)h->I * h->L * 4 * 3                                  // input + history r/w
+                      + (int64_t)h->C * h->L * 4                                      // output
+                      + (int64_t)h->C * 3 * h->L * 4 * 2;                             // overlap state r/w
   info->bank_bytes = h->bank_elems * (int64_t)h->store_bytes;
   info->delay_line_bytes = h->fdl_elems * (int64_t)h->store_bytes;
   info->workspace_bytes = (int64_t)h->n_rows * h->tile_width * 8;
   info->n_work_items = (int32_t)h->items.size();
   info->mac_chunk = h->chunk;
   info->mac_waves = h->shape.NW;
-  info->mac_grid = (int32_t)h->items.size();
+  info->mac_grid = grid_of(h);
+  info->fused = h->choice.fused;
+  info->n_cu = h->n_cu;
   return TVOLAP_OK;
 }
 

@@ -19,15 +19,48 @@ struct DevPlan {
   const int64_t* in_fdl_off;   // [I] start of input i in the delay line ([2][M_i][2L])
   const float2* tw;            // [4L] exp(-2 pi i t / 4L), from double precision
   const float* win;            // [2L] periodic Hann window, amplitude 1/2
+  const int32_t* ch_row_base;  // [C] first partial-spectrum row of channel c
+  const int32_t* ch_nchunks;   // [C] partition chunks of channel c (rows per tile)
+  const int32_t* in_ch_ptr;    // [I+1] channels of input i: in_ch[in_ch_ptr[i] .. in_ch_ptr[i+1])
+  const int32_t* in_ch;        // [C]
+  int32_t tile_width;          // bins per MAC tile (64 V)
 };
 
-// One unit of spectral-MAC work: a bin tile of up to 4 channels that share an
-// input, over the partitions [m0, m1). Channel g of the item writes its partial
-// spectrum tile to row (row + g) of the partial buffer.
+// One unit of per-block work. kind 1: the new spectrum of input `input`.
+// kind 0: spectral MAC of a bin tile of up to 4 channels that share an input,
+// over the partitions [max(m0, 1), m1) (chunk `chunk` of the channels'
+// partition range; the m = 0 term is added when the channel is completed).
+// Channel g writes its partial spectrum tile to row[g] of the partial buffer;
+// the rows of a channel are contiguous, ordered (tile, chunk).
 struct WorkItem {
   int32_t input, n_ch, m0, m1;
-  int32_t tile, row, pad0, pad1;
+  int32_t tile, chunk, kind, pad;
   int32_t ch[4];
+  int32_t row[4];
+};
+
+// Everything the fused per-block kernel touches.
+struct BlockArgs {
+  DevPlan P;
+  const WorkItem* items;
+  int32_t n_items;
+  const void* bank;
+  void* fdl;
+  const int32_t* sel;          // slots of this block (caller's device array or the handle's)
+  int32_t* sel_store;          // handle's selection, updated when sel is the caller's
+  int32_t copy_sel;
+  const float* in;
+  int64_t in_stride;
+  float* hist;                 // [2][I][L]
+  float2* ypart;               // [rows][tile_width]
+  int32_t* arrive;             // [C] work items finished per channel in this block
+  const int32_t* needed;       // [C] work items per channel
+  int32_t* done;               // [1] work items finished in this block
+  float* ola;                  // [C][3L]
+  float* out;
+  int64_t out_stride;
+  uint64_t* counter;           // calls processed so far
+  int32_t inverse_inline;      // 1: last item of a channel transforms back; 0: a later kernel does
 };
 
 struct MacShape {
@@ -42,9 +75,10 @@ hipError_t launch_fwd(const DevPlan& P, int dtype, const float* in, int64_t in_s
 hipError_t launch_mac(const DevPlan& P, int dtype, const MacShape& shape, const WorkItem* items,
                       int n_items, const void* bank, const void* fdl, const int32_t* sel,
                       float2* ypart, const uint64_t* counter, hipStream_t s);
-hipError_t launch_inv(const DevPlan& P, int tile_width, const float2* ypart, const int32_t* rows_ptr,
-                      const int32_t* rows, float* ola, float* out, int64_t out_stride,
-                      const int32_t* sel_in, int32_t* sel_store, uint64_t* counter, hipStream_t s);
+hipError_t launch_inv(const DevPlan& P, int dtype, const float2* ypart, const void* bank, const void* fdl,
+                      const int32_t* sel, float* ola, float* out, int64_t out_stride, int32_t copy_sel,
+                      int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s);
+hipError_t launch_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s);
 hipError_t launch_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M,
                          void* dst, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -1,39 +1,33 @@
 // gfx950 kernels of the TVOLAP hot path (Jaeger et al., arXiv 2310.00319, Sec. 2).
 //
-//   k_fwd     Hann-weighted 2L block (eq. 1-2), zero pad to 4L (eq. 5), real
-//             4L-point DFT (eq. 4) via a 2L-point complex FFT in LDS; the new
-//             spectrum goes into its delay-line slot.
-//   k_mac     spectral MAC of eq. 8: Y = sum_m H_{g(l)}(m) X(l - 2m), streamed
+// Fused path (one launch per block):
+//   k_block   Two kinds of work item. Spectrum items (one per input) build the
+//             new input spectrum: Hann-weighted 2L block (eq. 1-2), zero pad to
+//             4L (eq. 5), real 4L-point DFT (eq. 4), stored in the delay line.
+//             MAC items cover (input, up to 4 channels of that input, bin tile,
+//             chunk of partitions m >= 1): the spectral MAC of eq. 8 streamed
 //             from HBM in 16-byte lanes, FP32 accumulation, partitions split
-//             across the waves of a workgroup and reduced through LDS.
-//   k_inv     sums the partial spectra of a channel, inverse DFT (eq. 9) via a
-//             2L-point complex FFT, overlap-add at hop L (eq. 10-13).
+//             across the waves and reduced in LDS, partial spectrum tiles
+//             written out. The last item to arrive for a channel (device-scope
+//             counter; no item ever waits for another) adds the m = 0 term,
+//             sums the channel's partial tiles, runs the inverse DFT (eq. 9) and
+//             the overlap-add at hop L (eq. 10-13).
+// Plain path (three launches per block, the unfused baseline):
+//   k_fwd, k_mac, k_inv with the same arithmetic.
 //   k_irprep  IR partition spectra (eq. 3, 6-7) into a bank slot.
-//
-// The complex FFT is a Stockham autosort FFT with radix-8/4 stages and one LDS
-// ping-pong per stage. A real 4L-point transform is done as a 2L-point complex
-// transform of z(n) = x(2n) + i x(2n+1) plus a post-processing pass; the
-// inverse runs the same steps backwards. Twiddles come from a table computed in
-// double precision on the host.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#include "fft_lds.hpp"
 #include "tvolap_internal.h"
 
 namespace tvx {
 namespace {
 
-// ---------------------------------------------------------------- complex helpers
-
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
-__device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }   // a * (-i)
-__device__ __forceinline__ float2 cmul_pi(float2 a) { return make_float2(-a.y, a.x); }   // a * (+i)
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+using fft::cadd;
+using fft::cmul;
 
 // ---------------------------------------------------------------- storage types
 
@@ -66,10 +60,12 @@ template <> __device__ __forceinline__ uint32_t pack<2>(float2 v) {
   return f32_to_f16_rne(v.x) | (f32_to_f16_rne(v.y) << 16);
 }
 
-__device__ __forceinline__ float2 unpack_bf16(uint32_t w) {
+template <int DT> __device__ __forceinline__ float2 unpack(typename Store<DT>::T w);
+template <> __device__ __forceinline__ float2 unpack<0>(float2 w) { return w; }
+template <> __device__ __forceinline__ float2 unpack<1>(uint32_t w) {
   return make_float2(bf16_to_f32(w & 0xffffu), bf16_to_f32(w >> 16));
 }
-__device__ __forceinline__ float2 unpack_f16(uint32_t w) {
+template <> __device__ __forceinline__ float2 unpack<2>(uint32_t w) {
   return make_float2(f16_to_f32(w), f16_to_f32(w >> 16));
 }
 
@@ -77,212 +73,122 @@ __device__ __forceinline__ float2 unpack_f16(uint32_t w) {
 template <int DT, int V>
 __device__ __forceinline__ void load_vec(const typename Store<DT>::T* __restrict__ p, float2 (&o)[V]) {
   if constexpr (DT == 0) {
-    if constexpr (V == 1) {
-      o[0] = *p;
-    } else {
 #pragma unroll
-      for (int j = 0; j < V; j += 2) {
-        float4 t = *reinterpret_cast<const float4*>(p + j);
-        o[j] = make_float2(t.x, t.y);
-        o[j + 1] = make_float2(t.z, t.w);
-      }
+    for (int j = 0; j < V; j += 2) {
+      const float4 t = *reinterpret_cast<const float4*>(p + j);
+      o[j] = make_float2(t.x, t.y);
+      o[j + 1] = make_float2(t.z, t.w);
     }
   } else {
     uint32_t w[V];
-    if constexpr (V == 1) {
-      w[0] = *p;
-    } else if constexpr (V == 2) {
-      uint2 t = *reinterpret_cast<const uint2*>(p);
+    if constexpr (V == 2) {
+      const uint2 t = *reinterpret_cast<const uint2*>(p);
       w[0] = t.x; w[1] = t.y;
     } else {
 #pragma unroll
       for (int j = 0; j < V; j += 4) {
-        uint4 t = *reinterpret_cast<const uint4*>(p + j);
+        const uint4 t = *reinterpret_cast<const uint4*>(p + j);
         w[j] = t.x; w[j + 1] = t.y; w[j + 2] = t.z; w[j + 3] = t.w;
       }
     }
 #pragma unroll
-    for (int j = 0; j < V; ++j) o[j] = (DT == 1) ? unpack_bf16(w[j]) : unpack_f16(w[j]);
+    for (int j = 0; j < V; ++j) o[j] = unpack<DT>(w[j]);
   }
 }
 
-// ---------------------------------------------------------------- small DFTs (forward sign)
-
-template <int R> __device__ __forceinline__ void dft(float2 (&v)[R]);
-
-template <> __device__ __forceinline__ void dft<2>(float2 (&v)[2]) {
-  float2 a = v[0], b = v[1];
-  v[0] = cadd(a, b);
-  v[1] = csub(a, b);
+// Device-coherent publication of partial spectra between workgroups of one
+// launch. Relaxed agent-scope atomic stores and loads of the 8-byte values are
+// performed at the device coherence point (they are not kept in, or served
+// from, the non-coherent per-XCD L2), so a writer that waits for its stores to
+// complete before incrementing a counter, and a reader that loads after seeing
+// that increment, need no cache-wide write-back or invalidate.
+__device__ __forceinline__ void store_coherent(float2* p, float2 v) {
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
 }
-
-template <> __device__ __forceinline__ void dft<4>(float2 (&v)[4]) {
-  float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-  float2 t2 = cadd(v[1], v[3]), t3 = cmul_mi(csub(v[1], v[3]));
-  v[0] = cadd(t0, t2);
-  v[2] = csub(t0, t2);
-  v[1] = cadd(t1, t3);
-  v[3] = csub(t1, t3);
+__device__ __forceinline__ void store_coherent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ float2 load_coherent(const float2* p) {
+  return __builtin_bit_cast(
+      float2, __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ uint32_t load_coherent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool COHERENT, typename T>
+__device__ __forceinline__ void store_maybe(T* p, T v) {
+  if constexpr (COHERENT) store_coherent(p, v); else *p = v;
+}
+template <bool COHERENT, typename T>
+__device__ __forceinline__ T load_maybe(const T* p) {
+  if constexpr (COHERENT) return load_coherent(p); else return *p;
+}
+// Wait until every memory operation of this wave has completed.
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-template <> __device__ __forceinline__ void dft<8>(float2 (&v)[8]) {
-  constexpr float c = 0.70710678118654752440f;
-  float2 e[4] = {v[0], v[2], v[4], v[6]};
-  float2 o[4] = {v[1], v[3], v[5], v[7]};
-  dft<4>(e);
-  dft<4>(o);
-  // o[k] *= exp(-2 pi i k / 8)
-  o[1] = make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
-  o[2] = cmul_mi(o[2]);
-  o[3] = make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+// ---------------------------------------------------------------- shared steps
+
+// Twiddles exp(-2 pi i t / 4L) (t < 4L) and the window (2L) into LDS.
+template <int L, int T>
+__device__ __forceinline__ void load_tables(const DevPlan& P, float2* twl, float* winl, int tid) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[k] = cadd(e[k], o[k]);
-    v[k + 4] = csub(e[k], o[k]);
-  }
-}
-
-// ---------------------------------------------------------------- Stockham stages
-
-// One radix-R stage of an N-point forward FFT run by T threads. NS is the
-// product of the radices of the earlier stages. `tw` holds exp(-2 pi i t / 2N).
-template <int N, int R, int NS, int T>
-__device__ __forceinline__ void stage(const float2* __restrict__ src, float2* __restrict__ dst,
-                                      const float2* __restrict__ tw, int tid) {
-  constexpr int NB = N / R;
-  constexpr int TWS = 2 * (N / (NS * R));
+  for (int i = tid; i < 4 * L; i += T) twl[i] = P.tw[i];
 #pragma unroll
-  for (int j0 = 0; j0 < NB; j0 += T) {
-    const int j = j0 + tid;
-    if ((NB % T == 0) || j < NB) {
-      const int k = j & (NS - 1);
-      float2 v[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = src[j + r * NB];
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * TWS]);
-      }
-      dft<R>(v);
-      const int base = (j - k) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst[base + r * NS] = v[r];
-    }
-  }
+  for (int i = tid; i < 2 * L; i += T) winl[i] = P.win[i];
 }
 
-// N-point forward complex FFT of `a` (LDS); `b` is scratch of the same size.
-// Returns the buffer that holds the result. Callers synchronise before.
-template <int N, int T>
-__device__ __forceinline__ float2* fft_fwd(float2* a, float2* b, const float2* tw, int tid) {
-  if constexpr (N == 128) {
-    stage<128, 8, 1, T>(a, b, tw, tid); __syncthreads();
-    stage<128, 4, 8, T>(b, a, tw, tid); __syncthreads();
-    stage<128, 4, 32, T>(a, b, tw, tid); __syncthreads();
-    return b;
-  } else if constexpr (N == 256) {
-    stage<256, 8, 1, T>(a, b, tw, tid); __syncthreads();
-    stage<256, 8, 8, T>(b, a, tw, tid); __syncthreads();
-    stage<256, 4, 64, T>(a, b, tw, tid); __syncthreads();
-    return b;
-  } else if constexpr (N == 512) {
-    stage<512, 8, 1, T>(a, b, tw, tid); __syncthreads();
-    stage<512, 8, 8, T>(b, a, tw, tid); __syncthreads();
-    stage<512, 8, 64, T>(a, b, tw, tid); __syncthreads();
-    return b;
-  } else {
-    static_assert(N == 1024, "unsupported FFT size");
-    stage<1024, 8, 1, T>(a, b, tw, tid); __syncthreads();
-    stage<1024, 8, 8, T>(b, a, tw, tid); __syncthreads();
-    stage<1024, 4, 64, T>(a, b, tw, tid); __syncthreads();
-    stage<1024, 4, 256, T>(b, a, tw, tid); __syncthreads();
-    return a;
-  }
-}
+// Block counter -> delay-line position: parity p of the call, slot q within
+// the parity's ring of M_i spectra.
+__device__ __forceinline__ int ring_slot(uint64_t cnt, int Mi) { return (int)((cnt >> 1) % (uint64_t)Mi); }
 
-// Packed bin k of the real 4L-point DFT from Z = FFT_2L(x(2n) + i x(2n+1)).
-// N = 2L. Slot 0 packs the two real bins (X(0), X(2L)).
-template <int N>
-__device__ __forceinline__ float2 real_fwd_post(const float2* Z, int k, const float2* tw) {
-  if (k == 0) {
-    const float2 z = Z[0];
-    return make_float2(z.x + z.y, z.x - z.y);
-  }
-  const float2 A = Z[k];
-  const float2 B = cconj(Z[N - k]);
-  const float2 E = cscale(cadd(A, B), 0.5f);
-  const float2 D = cscale(csub(A, B), 0.5f);
-  return cadd(E, cmul_mi(cmul(tw[k], D)));
-}
-
-// conj of Z'(k), the 2L-point spectrum whose inverse transform interleaves the
-// even and odd samples of the real inverse DFT of the packed spectrum Y.
-template <int N>
-__device__ __forceinline__ float2 real_inv_pre_conj(const float2* Y, int k, const float2* tw) {
-  if (k == 0) {
-    const float2 y = Y[0];
-    return make_float2(y.x + y.y, -(y.x - y.y));
-  }
-  const float2 A = Y[k];
-  const float2 B = cconj(Y[N - k]);
-  const float2 S = cadd(A, B);
-  const float2 D = csub(A, B);
-  const float2 Zp = cadd(S, cmul_pi(cmul(cconj(tw[k]), D)));
-  return cconj(Zp);
-}
-
-// ---------------------------------------------------------------- kernels
-
-// One workgroup (one wave) per input: window, transform, store in the delay line.
-template <int L, int DT>
-__global__ __launch_bounds__(64) void k_fwd(DevPlan P, const float* __restrict__ in, int64_t in_stride,
-                                            float* __restrict__ hist, typename Store<DT>::T* __restrict__ fdl,
-                                            const uint64_t* __restrict__ counter) {
+// New input spectrum of input i (eq. 1, 2, 4, 5): the 2L-sample block (the
+// previous L samples, history parity p^1, then the L new ones) weighted by the
+// window, zero padded to 4L and transformed; the packed spectrum, rounded to
+// the storage type, goes to delay-line slot (p, q). The new samples become the
+// history of parity p. COHERENT: publish for readers in the same launch.
+template <int L, int T, int DT, bool COHERENT>
+__device__ __forceinline__ void input_spectrum(const DevPlan& P, const float* __restrict__ in, int64_t in_stride,
+                                               float* __restrict__ hist, typename Store<DT>::T* __restrict__ fdl,
+                                               int i, int p, uint64_t cnt, const float2* twl, const float* winl,
+                                               float2* bufA, float2* bufB, int tid) {
   constexpr int N = 2 * L;
-  __shared__ float2 bufA[N];
-  __shared__ float2 bufB[N];
-  const int i = blockIdx.x;
-  const int tid = threadIdx.x;
-  const uint64_t c = *counter;
-  const int p = (int)(c & 1u);
-  const int Mi = P.in_M[i];
-  const int q = (int)((c >> 1) % (uint64_t)Mi);
   const float* hold = hist + ((size_t)(p ^ 1) * P.I + i) * L;
   float* hnew = hist + ((size_t)p * P.I + i) * L;
   const float* xin = in + (int64_t)i * in_stride;
-
-  for (int n = tid; n < L; n += 64) {
+#pragma unroll
+  for (int n = tid; n < L; n += T) {
     const int t0 = 2 * n, t1 = 2 * n + 1;
     const float s0 = (t0 < L) ? hold[t0] : xin[t0 - L];
     const float s1 = (t1 < L) ? hold[t1] : xin[t1 - L];
-    bufA[n] = make_float2(P.win[t0] * s0, P.win[t1] * s1);
+    bufA[n] = make_float2(winl[t0] * s0, winl[t1] * s1);
     bufA[n + L] = make_float2(0.f, 0.f);
   }
-  for (int n = tid; n < L; n += 64) hnew[n] = xin[n];
+#pragma unroll
+  for (int n = tid; n < L; n += T) hnew[n] = xin[n];
   __syncthreads();
-  const float2* Z = fft_fwd<N, 64>(bufA, bufB, P.tw, tid);
-  typename Store<DT>::T* dst = fdl + P.in_fdl_off[i] + ((int64_t)p * Mi + q) * N;
-  for (int k = tid; k < N; k += 64) dst[k] = pack<DT>(real_fwd_post<N>(Z, k, P.tw));
+  const float2* Z = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  const int Mi = P.in_M[i];
+  typename Store<DT>::T* dst = fdl + P.in_fdl_off[i] + ((int64_t)p * Mi + ring_slot(cnt, Mi)) * N;
+#pragma unroll
+  for (int k = tid; k < N; k += T) store_maybe<COHERENT>(dst + k, pack<DT>(fft::real_fwd_post<N>(Z, k, twl)));
 }
 
-// Spectral MAC over one work item per workgroup.
+// Spectral MAC of one work item (eq. 8) over partitions m >= 1 of its range:
+// acc[g] += H_{c_g, slot}(m) X(l - 2m) for this lane's V bins. The waves of the
+// workgroup take every NW-th partition; two partitions are in flight per wave.
+// The packed bin 0 holds two real bins and multiplies component-wise.
 template <int V, int G, int NW, int DT>
-__global__ __launch_bounds__(64 * NW) void k_mac(DevPlan P, const WorkItem* __restrict__ items,
-                                                 const typename Store<DT>::T* __restrict__ bank,
-                                                 const typename Store<DT>::T* __restrict__ fdl,
-                                                 const int32_t* __restrict__ sel, float2* __restrict__ ypart,
-                                                 const uint64_t* __restrict__ counter) {
+__device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
+                                         const typename Store<DT>::T* __restrict__ bank,
+                                         const typename Store<DT>::T* __restrict__ fdl,
+                                         const int32_t* __restrict__ sel, int p, uint64_t cnt, int lane, int w,
+                                         float2 (&acc)[G][V]) {
   using ST = typename Store<DT>::T;
   constexpr int TW = 64 * V;
-  __shared__ float2 red[NW][G][TW];
-  const WorkItem it = items[blockIdx.x];
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
   const int N = 2 * P.L;
-  const uint64_t c = *counter;
-  const int p = (int)(c & 1u);
   const int Mi = P.in_M[it.input];
-  const int q = (int)((c >> 1) % (uint64_t)Mi);
+  const int q = ring_slot(cnt, Mi);
   const int kbase = it.tile * TW + lane * V;
   const ST* xrow = fdl + P.in_fdl_off[it.input] + (int64_t)p * Mi * N + kbase;
   const ST* hrow[G];
@@ -301,13 +207,42 @@ __global__ __launch_bounds__(64 * NW) void k_mac(DevPlan P, const WorkItem* __re
     }
   }
   const bool dc_lane = (kbase == 0);
-  float2 acc[G][V];
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[g][v] = make_float2(0.f, 0.f);
 
-  for (int m = it.m0 + w; m < it.m1; m += NW) {
+  auto accumulate = [&](int g, const float2 (&H)[V], const float2 (&X)[V]) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      float2 prod = cmul(H[v], X[v]);
+      if (v == 0 && dc_lane) prod = make_float2(H[0].x * X[0].x, H[0].y * X[0].y);
+      acc[g][v] = cadd(acc[g][v], prod);
+    }
+  };
+  int m = (it.m0 > 1 ? it.m0 : 1) + w;
+  for (; m + NW < it.m1; m += 2 * NW) {
+    const int m2 = m + NW;
+    int xr1 = q - m;
+    if (xr1 < 0) xr1 += Mi;
+    int xr2 = q - m2;
+    if (xr2 < 0) xr2 += Mi;
+    float2 X1[V], X2[V];
+    float2 H1[G][V], H2[G][V];
+    load_vec<DT, V>(xrow + (int64_t)xr1 * N, X1);
+    load_vec<DT, V>(xrow + (int64_t)xr2 * N, X2);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (m < Mc[g]) load_vec<DT, V>(hrow[g] + (int64_t)m * N, H1[g]);
+      if (m2 < Mc[g]) load_vec<DT, V>(hrow[g] + (int64_t)m2 * N, H2[g]);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (m < Mc[g]) accumulate(g, H1[g], X1);
+      if (m2 < Mc[g]) accumulate(g, H2[g], X2);
+    }
+  }
+  if (m < it.m1) {
     int xr = q - m;
     if (xr < 0) xr += Mi;
     float2 X[V];
@@ -317,78 +252,277 @@ __global__ __launch_bounds__(64 * NW) void k_mac(DevPlan P, const WorkItem* __re
       if (m < Mc[g]) {
         float2 H[V];
         load_vec<DT, V>(hrow[g] + (int64_t)m * N, H);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          float2 prod = cmul(H[v], X[v]);
-          if (v == 0 && dc_lane) prod = make_float2(H[0].x * X[0].x, H[0].y * X[0].y);
-          acc[g][v] = cadd(acc[g][v], prod);
-        }
+        accumulate(g, H, X);
       }
     }
   }
+}
+
+// Reduce the waves' accumulators through LDS and write the item's partial
+// spectrum tiles (row[g] of the partial buffer).
+template <int V, int G, int NW, bool COHERENT>
+__device__ __forceinline__ void write_partials(const WorkItem& it, float2 (&acc)[G][V], float2 (*red)[G][64 * V],
+                                               float2* __restrict__ ypart, int lane, int w, int tid) {
+  constexpr int TW = 64 * V;
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int v = 0; v < V; ++v) red[w][g][lane * V + v] = acc[g][v];
   __syncthreads();
-  for (int idx = threadIdx.x; idx < G * TW; idx += 64 * NW) {
-    const int g = idx / TW;
-    const int b = idx - g * TW;
+  for (int e = tid; e < G * TW; e += 64 * NW) {
+    const int g = e / TW;
+    const int b = e - g * TW;
     if (g < it.n_ch) {
       float2 s = red[0][g][b];
 #pragma unroll
       for (int ww = 1; ww < NW; ++ww) s = cadd(s, red[ww][g][b]);
-      ypart[(int64_t)(it.row + g) * TW + b] = s;
+      store_maybe<COHERENT>(ypart + (int64_t)it.row[g] * TW + b, s);
     }
   }
 }
 
-// One workgroup per channel: gather the spectrum, inverse transform, overlap-add.
-template <int L>
-__global__ __launch_bounds__(64) void k_inv(DevPlan P, int TW, const float2* __restrict__ ypart,
-                                            const int32_t* __restrict__ rows_ptr, const int32_t* __restrict__ rows,
-                                            float* __restrict__ ola, float* __restrict__ out, int64_t out_stride,
-                                            const int32_t* __restrict__ sel_in, int32_t* __restrict__ sel_store,
+// Inverse real DFT of the packed spectrum Y (eq. 9) and overlap-add (eq. 10-13):
+// out(n) = state(n) + y(n) for n < L, state'(n) = state(n + L) + y(n + L) for
+// n < 2L, state'(2L + n) = y(3L + n) for n < L. Y, bufA, bufB in LDS.
+template <int L, int T>
+__device__ __forceinline__ void inverse_ola(float2* Y, float2* bufA, float2* bufB, const float2* twl,
+                                            float* __restrict__ st, float* __restrict__ o, int tid) {
+  constexpr int N = 2 * L;
+  constexpr int NPT = (4 * L + T - 1) / T;
+  float old[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int n = tid + j * T;
+    old[j] = (n < 3 * L) ? st[n] : 0.f;
+  }
+#pragma unroll
+  for (int k = tid; k < N; k += T) bufA[k] = fft::real_inv_pre_conj<N>(Y, k, twl);
+  __syncthreads();
+  const float2* R = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  constexpr float scale = 1.0f / (float)(4 * L);
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int n = tid + j * T;
+    if (n < 4 * L) {
+      const float2 z = R[n >> 1];
+      const float yv = ((n & 1) ? -z.y : z.x) * scale;
+      if (n < L) {
+        o[n] = old[j] + yv;
+      } else if (n < 3 * L) {
+        st[n - L] = old[j] + yv;
+      } else {
+        st[n - L] = yv;
+      }
+    }
+  }
+}
+
+// Complete channel c: Y = sum of its partial tiles (partitions m >= 1) +
+// H_{c, slot}(0) X(l) (eq. 8, m = 0 term, X(l) read back from the delay
+// line), then transform back and overlap-add. COHERENT: the partial tiles and
+// X(l) were published by other workgroups of the same launch.
+template <int L, int T, int DT, bool COHERENT>
+__device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __restrict__ ypart,
+                                              const typename Store<DT>::T* __restrict__ bank,
+                                              const typename Store<DT>::T* __restrict__ fdl,
+                                              const int32_t* __restrict__ sel, int c, int p, uint64_t cnt,
+                                              float2* Y, float2* bufA, float2* bufB, const float2* twl,
+                                              float* __restrict__ ola, float* __restrict__ out, int64_t out_stride,
+                                              int tid) {
+  using ST = typename Store<DT>::T;
+  constexpr int N = 2 * L;
+  const int TW = P.tile_width;
+  const int base = P.ch_row_base[c];
+  const int nch = P.ch_nchunks[c];
+  const int i = P.ch_input[c];
+  const int Mi = P.in_M[i];
+  const ST* xrow = fdl + P.in_fdl_off[i] + ((int64_t)p * Mi + ring_slot(cnt, Mi)) * N;
+  int s = sel[c];
+  s = s < 0 ? 0 : (s >= P.K ? P.K - 1 : s);
+  const ST* h0 = bank + P.ch_bank_off[c] + (int64_t)s * P.ch_M[c] * N;
+#pragma unroll
+  for (int k = tid; k < N; k += T) {
+    const float2 X = unpack<DT>(load_maybe<COHERENT>(xrow + k));
+    const float2 H = unpack<DT>(h0[k]);
+    float2 s0 = (k == 0) ? make_float2(H.x * X.x, H.y * X.y) : cmul(H, X);
+    float2 s1 = make_float2(0.f, 0.f), s2 = s1, s3 = s1;
+    const int t = k / TW;
+    const int b = k - t * TW;
+    const float2* src = ypart + ((int64_t)base + (int64_t)t * nch) * TW + b;
+    int j = 0;
+    for (; j + 4 <= nch; j += 4) {
+      const float2 a0 = load_maybe<COHERENT>(src + (int64_t)(j + 0) * TW);
+      const float2 a1 = load_maybe<COHERENT>(src + (int64_t)(j + 1) * TW);
+      const float2 a2 = load_maybe<COHERENT>(src + (int64_t)(j + 2) * TW);
+      const float2 a3 = load_maybe<COHERENT>(src + (int64_t)(j + 3) * TW);
+      s0 = cadd(s0, a0); s1 = cadd(s1, a1); s2 = cadd(s2, a2); s3 = cadd(s3, a3);
+    }
+    for (; j < nch; ++j) s0 = cadd(s0, load_maybe<COHERENT>(src + (int64_t)j * TW));
+    Y[k] = cadd(cadd(s0, s1), cadd(s2, s3));
+  }
+  __syncthreads();
+  inverse_ola<L, T>(Y, bufA, bufB, twl, ola + (int64_t)c * 3 * L, out + (int64_t)c * out_stride, tid);
+}
+
+// ---------------------------------------------------------------- fused per-block kernel
+
+// Work items: kind 1 = new spectrum of one input (placed first), kind 0 = MAC
+// over a partition chunk of up to G channels sharing an input. Every channel
+// waits for needed[c] arrivals (its MAC items plus its input's spectrum item);
+// the item that arrives last completes the channel. No item ever waits.
+template <int L, int V, int G, int NW, int DT>
+__global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
+  using ST = typename Store<DT>::T;
+  constexpr int N = 2 * L;
+  constexpr int T = 64 * NW;
+  constexpr int TW = 64 * V;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  __shared__ float2 ybuf[N];
+  __shared__ float2 red[NW][G][TW];
+  __shared__ int flag;
+  const DevPlan& P = A.P;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const uint64_t cnt = *A.counter;
+  const int p = (int)(cnt & 1u);
+  const ST* bank = static_cast<const ST*>(A.bank);
+  ST* fdl = static_cast<ST*>(A.fdl);
+  const bool inl = A.inverse_inline != 0;
+  bool tables = false;
+
+  // Count one arrival for channel c; if it was the last one, complete c.
+  auto arrive = [&](int c) {
+    if (tid == 0) flag = (atomicAdd(&A.arrive[c], 1) == A.needed[c] - 1) ? 1 : 0;
+    __syncthreads();
+    if (flag) {
+      if (!tables) {
+        load_tables<L, T>(P, twl, winl, tid);
+        tables = true;
+      }
+      channel_final<L, T, DT, true>(P, A.ypart, bank, fdl, A.sel, c, p, cnt, ybuf, bufA, bufB, twl, A.ola, A.out,
+                                    A.out_stride, tid);
+      if (tid == 0) {
+        A.arrive[c] = 0;
+        if (A.copy_sel) A.sel_store[c] = A.sel[c];
+      }
+    }
+    __syncthreads();
+  };
+
+  for (int idx = blockIdx.x; idx < A.n_items; idx += gridDim.x) {
+    const WorkItem it = A.items[idx];
+    if (it.kind == 1) {
+      if (!tables) {
+        load_tables<L, T>(P, twl, winl, tid);
+        tables = true;
+        __syncthreads();
+      }
+      if (inl) {
+        input_spectrum<L, T, DT, true>(P, A.in, A.in_stride, A.hist, fdl, it.input, p, cnt, twl, winl, bufA, bufB,
+                                       tid);
+        wait_memory();
+        __syncthreads();
+        for (int j = P.in_ch_ptr[it.input]; j < P.in_ch_ptr[it.input + 1]; ++j) arrive(P.in_ch[j]);
+      } else {
+        input_spectrum<L, T, DT, false>(P, A.in, A.in_stride, A.hist, fdl, it.input, p, cnt, twl, winl, bufA, bufB,
+                                        tid);
+        __syncthreads();
+        continue;
+      }
+    } else {
+      float2 acc[G][V];
+      mac_item<V, G, NW, DT>(P, it, bank, fdl, A.sel, p, cnt, lane, w, acc);
+      if (inl) {
+        write_partials<V, G, NW, true>(it, acc, red, A.ypart, lane, w, tid);
+        wait_memory();
+        __syncthreads();
+        for (int g = 0; g < it.n_ch; ++g) arrive(it.ch[g]);
+      } else {
+        write_partials<V, G, NW, false>(it, acc, red, A.ypart, lane, w, tid);
+        __syncthreads();
+        continue;
+      }
+    }
+    if (tid == 0) {
+      if (atomicAdd(A.done, 1) == A.n_items - 1) {
+        // every item has finished, so every workgroup has read the call count
+        *A.done = 0;
+        *A.counter = cnt + 1u;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- plain path
+
+// One workgroup (one wave) per input: new input spectrum into the delay line.
+template <int L, int DT>
+__global__ __launch_bounds__(64) void k_fwd(DevPlan P, const float* __restrict__ in, int64_t in_stride,
+                                            float* __restrict__ hist, typename Store<DT>::T* __restrict__ fdl,
+                                            const uint64_t* __restrict__ counter) {
+  constexpr int N = 2 * L;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  const int tid = threadIdx.x;
+  const uint64_t cnt = *counter;
+  load_tables<L, 64>(P, twl, winl, tid);
+  __syncthreads();
+  input_spectrum<L, 64, DT, false>(P, in, in_stride, hist, fdl, blockIdx.x, (int)(cnt & 1u), cnt, twl, winl, bufA,
+                                   bufB, tid);
+}
+
+// One workgroup per MAC work item: partial spectrum tiles.
+template <int V, int G, int NW, int DT>
+__global__ __launch_bounds__(64 * NW) void k_mac(DevPlan P, const WorkItem* __restrict__ items,
+                                                 const typename Store<DT>::T* __restrict__ bank,
+                                                 const typename Store<DT>::T* __restrict__ fdl,
+                                                 const int32_t* __restrict__ sel, float2* __restrict__ ypart,
+                                                 const uint64_t* __restrict__ counter) {
+  __shared__ float2 red[NW][G][64 * V];
+  const WorkItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const uint64_t cnt = *counter;
+  float2 acc[G][V];
+  mac_item<V, G, NW, DT>(P, it, bank, fdl, sel, (int)(cnt & 1u), cnt, tid & 63, tid >> 6, acc);
+  write_partials<V, G, NW, false>(it, acc, red, ypart, tid & 63, tid >> 6, tid);
+}
+
+// One workgroup per channel: complete the channel; the last workgroup to
+// finish advances the call count.
+template <int L, int DT>
+__global__ __launch_bounds__(64) void k_inv(DevPlan P, const float2* __restrict__ ypart,
+                                            const typename Store<DT>::T* __restrict__ bank,
+                                            const typename Store<DT>::T* __restrict__ fdl,
+                                            const int32_t* __restrict__ sel, float* __restrict__ ola,
+                                            float* __restrict__ out, int64_t out_stride, int32_t copy_sel,
+                                            int32_t* __restrict__ sel_store, int32_t* __restrict__ done,
                                             uint64_t* __restrict__ counter) {
   constexpr int N = 2 * L;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
   __shared__ float2 Y[N];
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
-  const int T = N / TW;
-  for (int k = tid; k < N; k += 64) {
-    const int t = k / TW;
-    const int b = k - t * TW;
-    float2 s = make_float2(0.f, 0.f);
-    const int r0 = rows_ptr[c * T + t], r1 = rows_ptr[c * T + t + 1];
-    for (int r = r0; r < r1; ++r) s = cadd(s, ypart[(int64_t)rows[r] * TW + b]);
-    Y[k] = s;
-  }
-  __syncthreads();
-  for (int k = tid; k < N; k += 64) bufA[k] = real_inv_pre_conj<N>(Y, k, P.tw);
-  __syncthreads();
-  const float2* R = fft_fwd<N, 64>(bufA, bufB, P.tw, tid);
-  // y(2n) = Re z(n) / 4L, y(2n+1) = Im z(n) / 4L with z = conj(R)
-  constexpr float scale = 1.0f / (float)(4 * L);
-  float* old = reinterpret_cast<float*>(Y);   // 4L floats of room, 3L used
-  float* st = ola + (int64_t)c * 3 * L;
-  for (int n = tid; n < 3 * L; n += 64) old[n] = st[n];
-  __syncthreads();
-  float* o = out + (int64_t)c * out_stride;
-  for (int n = tid; n < 4 * L; n += 64) {
-    const float2 z = R[n >> 1];
-    const float yv = ((n & 1) ? -z.y : z.x) * scale;
-    if (n < L) {
-      o[n] = old[n] + yv;
-    } else if (n < 3 * L) {
-      st[n - L] = old[n] + yv;
-    } else {
-      st[n - L] = yv;
+  const uint64_t cnt = *counter;
+  load_tables<L, 64>(P, twl, winl, tid);
+  channel_final<L, 64, DT, false>(P, ypart, bank, fdl, sel, c, (int)(cnt & 1u), cnt, Y, bufA, bufB, twl, ola, out,
+                                  out_stride, tid);
+  if (tid == 0) {
+    if (copy_sel) sel_store[c] = sel[c];
+    if (atomicAdd(done, 1) == (int)gridDim.x - 1) {
+      *done = 0;
+      *counter = cnt + 1u;
     }
   }
-  if (tid == 0 && sel_in != nullptr) sel_store[c] = sel_in[c];
-  if (c == 0 && tid == 0) *counter = *counter + 1u;
 }
 
 // One workgroup per partition: spectra of the 2L-tap partitions of one IR.
@@ -396,10 +530,13 @@ template <int L, int DT>
 __global__ __launch_bounds__(64) void k_irprep(DevPlan P, const float* __restrict__ taps, int32_t n_taps,
                                                typename Store<DT>::T* __restrict__ dst) {
   constexpr int N = 2 * L;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
   const int m = blockIdx.x;
   const int tid = threadIdx.x;
+  load_tables<L, 64>(P, twl, winl, tid);
   for (int n = tid; n < L; n += 64) {
     const int t0 = 2 * L * m + 2 * n;
     const float h0 = (t0 < n_taps) ? taps[t0] : 0.f;
@@ -408,8 +545,8 @@ __global__ __launch_bounds__(64) void k_irprep(DevPlan P, const float* __restric
     bufA[n + L] = make_float2(0.f, 0.f);
   }
   __syncthreads();
-  const float2* Z = fft_fwd<N, 64>(bufA, bufB, P.tw, tid);
-  for (int k = tid; k < N; k += 64) dst[(int64_t)m * N + k] = pack<DT>(real_fwd_post<N>(Z, k, P.tw));
+  const float2* Z = fft::fft_fwd<N, 64>(bufA, bufB, twl, tid);
+  for (int k = tid; k < N; k += 64) dst[(int64_t)m * N + k] = pack<DT>(fft::real_fwd_post<N>(Z, k, twl));
 }
 
 __global__ __launch_bounds__(256) void k_fill_zero(uint4* __restrict__ p, size_t n16, uint8_t* __restrict__ tail,
@@ -420,141 +557,125 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint4* __restrict__ p, size_t
     for (size_t i = threadIdx.x; i < ntail; i += blockDim.x) tail[i] = 0;
 }
 
-// ---------------------------------------------------------------- dispatch helpers
+// ---------------------------------------------------------------- dispatch
 
-template <int L, int DT>
-hipError_t fwd_l(const DevPlan& P, const float* in, int64_t in_stride, float* hist, void* fdl,
-                 const uint64_t* counter, hipStream_t s) {
-  hipLaunchKernelGGL((k_fwd<L, DT>), dim3(P.I), dim3(64), 0, s, P, in, in_stride, hist,
-                     static_cast<typename Store<DT>::T*>(fdl), counter);
-  return hipGetLastError();
-}
-
-template <int DT>
-hipError_t fwd_dt(const DevPlan& P, const float* in, int64_t in_stride, float* hist, void* fdl,
-                  const uint64_t* counter, hipStream_t s) {
-  switch (P.L) {
-    case 64: return fwd_l<64, DT>(P, in, in_stride, hist, fdl, counter, s);
-    case 128: return fwd_l<128, DT>(P, in, in_stride, hist, fdl, counter, s);
-    case 256: return fwd_l<256, DT>(P, in, in_stride, hist, fdl, counter, s);
-    case 512: return fwd_l<512, DT>(P, in, in_stride, hist, fdl, counter, s);
+template <typename F>
+hipError_t by_hop(int L, F&& f) {
+  switch (L) {
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 128: return f(std::integral_constant<int, 128>{});
+    case 256: return f(std::integral_constant<int, 256>{});
+    case 512: return f(std::integral_constant<int, 512>{});
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int V, int G, int NW, int DT>
-hipError_t mac_inst(const DevPlan& P, const WorkItem* items, int n_items, const void* bank, const void* fdl,
-                    const int32_t* sel, float2* ypart, const uint64_t* counter, hipStream_t s) {
-  using ST = typename Store<DT>::T;
-  hipLaunchKernelGGL((k_mac<V, G, NW, DT>), dim3(n_items), dim3(64 * NW), 0, s, P, items,
-                     static_cast<const ST*>(bank), static_cast<const ST*>(fdl), sel, ypart, counter);
-  return hipGetLastError();
-}
-
-template <int V, int G, int DT>
-hipError_t mac_nw(const DevPlan& P, const MacShape& sh, const WorkItem* items, int n_items, const void* bank,
-                  const void* fdl, const int32_t* sel, float2* ypart, const uint64_t* counter, hipStream_t s) {
-  switch (sh.NW) {
-    case 4: return mac_inst<V, G, 4, DT>(P, items, n_items, bank, fdl, sel, ypart, counter, s);
-    case 8: return mac_inst<V, G, 8, DT>(P, items, n_items, bank, fdl, sel, ypart, counter, s);
+template <typename F>
+hipError_t by_dtype(int dt, F&& f) {
+  switch (dt) {
+    case 0: return f(std::integral_constant<int, 0>{});
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int V, int DT>
-hipError_t mac_g(const DevPlan& P, const MacShape& sh, const WorkItem* items, int n_items, const void* bank,
-                 const void* fdl, const int32_t* sel, float2* ypart, const uint64_t* counter, hipStream_t s) {
-  switch (sh.G) {
-    case 1: return mac_nw<V, 1, DT>(P, sh, items, n_items, bank, fdl, sel, ypart, counter, s);
-    case 2: return mac_nw<V, 2, DT>(P, sh, items, n_items, bank, fdl, sel, ypart, counter, s);
-    case 4: return mac_nw<V, 4, DT>(P, sh, items, n_items, bank, fdl, sel, ypart, counter, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int DT>
-hipError_t mac_v(const DevPlan& P, const MacShape& sh, const WorkItem* items, int n_items, const void* bank,
-                 const void* fdl, const int32_t* sel, float2* ypart, const uint64_t* counter, hipStream_t s) {
+template <typename F>
+hipError_t by_shape(const MacShape& sh, F&& f) {
+  auto nw = [&](auto V, auto G) -> hipError_t {
+    switch (sh.NW) {
+      case 4: return f(V, G, std::integral_constant<int, 4>{});
+      case 8: return f(V, G, std::integral_constant<int, 8>{});
+      default: return hipErrorInvalidValue;
+    }
+  };
+  auto g = [&](auto V) -> hipError_t {
+    switch (sh.G) {
+      case 1: return nw(V, std::integral_constant<int, 1>{});
+      case 2: return nw(V, std::integral_constant<int, 2>{});
+      case 4: return nw(V, std::integral_constant<int, 4>{});
+      default: return hipErrorInvalidValue;
+    }
+  };
   switch (sh.V) {
-    case 2: return mac_g<2, DT>(P, sh, items, n_items, bank, fdl, sel, ypart, counter, s);
-    case 4: return mac_g<4, DT>(P, sh, items, n_items, bank, fdl, sel, ypart, counter, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int L>
-hipError_t inv_l(const DevPlan& P, int TW, const float2* ypart, const int32_t* rows_ptr, const int32_t* rows,
-                 float* ola, float* out, int64_t out_stride, const int32_t* sel_in, int32_t* sel_store,
-                 uint64_t* counter, hipStream_t s) {
-  hipLaunchKernelGGL((k_inv<L>), dim3(P.C), dim3(64), 0, s, P, TW, ypart, rows_ptr, rows, ola, out, out_stride,
-                     sel_in, sel_store, counter);
-  return hipGetLastError();
-}
-
-template <int L, int DT>
-hipError_t irprep_l(const DevPlan& P, const float* taps, int32_t n_taps, int32_t M, void* dst, hipStream_t s) {
-  hipLaunchKernelGGL((k_irprep<L, DT>), dim3(M), dim3(64), 0, s, P, taps, n_taps,
-                     static_cast<typename Store<DT>::T*>(dst));
-  return hipGetLastError();
-}
-
-template <int DT>
-hipError_t irprep_dt(const DevPlan& P, const float* taps, int32_t n_taps, int32_t M, void* dst, hipStream_t s) {
-  switch (P.L) {
-    case 64: return irprep_l<64, DT>(P, taps, n_taps, M, dst, s);
-    case 128: return irprep_l<128, DT>(P, taps, n_taps, M, dst, s);
-    case 256: return irprep_l<256, DT>(P, taps, n_taps, M, dst, s);
-    case 512: return irprep_l<512, DT>(P, taps, n_taps, M, dst, s);
+    case 2: return g(std::integral_constant<int, 2>{});
+    case 4: return g(std::integral_constant<int, 4>{});
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-// ---------------------------------------------------------------- launchers
-
 hipError_t launch_fwd(const DevPlan& P, int dtype, const float* in, int64_t in_stride, float* hist, void* fdl,
                       const uint64_t* counter, hipStream_t s) {
-  switch (dtype) {
-    case 0: return fwd_dt<0>(P, in, in_stride, hist, fdl, counter, s);
-    case 1: return fwd_dt<1>(P, in, in_stride, hist, fdl, counter, s);
-    case 2: return fwd_dt<2>(P, in, in_stride, hist, fdl, counter, s);
-    default: return hipErrorInvalidValue;
-  }
+  return by_hop(P.L, [&](auto Lc) {
+    return by_dtype(dtype, [&](auto Dc) {
+      constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value;
+      hipLaunchKernelGGL((k_fwd<L, DT>), dim3(P.I), dim3(64), 0, s, P, in, in_stride, hist,
+                         static_cast<typename Store<DT>::T*>(fdl), counter);
+      return hipGetLastError();
+    });
+  });
 }
 
 hipError_t launch_mac(const DevPlan& P, int dtype, const MacShape& shape, const WorkItem* items, int n_items,
                       const void* bank, const void* fdl, const int32_t* sel, float2* ypart,
                       const uint64_t* counter, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  switch (dtype) {
-    case 0: return mac_v<0>(P, shape, items, n_items, bank, fdl, sel, ypart, counter, s);
-    case 1: return mac_v<1>(P, shape, items, n_items, bank, fdl, sel, ypart, counter, s);
-    case 2: return mac_v<2>(P, shape, items, n_items, bank, fdl, sel, ypart, counter, s);
-    default: return hipErrorInvalidValue;
-  }
+  return by_dtype(dtype, [&](auto Dc) {
+    return by_shape(shape, [&](auto Vc, auto Gc, auto NWc) {
+      constexpr int DT = decltype(Dc)::value, V = decltype(Vc)::value, G = decltype(Gc)::value,
+                    NW = decltype(NWc)::value;
+      using ST = typename Store<DT>::T;
+      hipLaunchKernelGGL((k_mac<V, G, NW, DT>), dim3(n_items), dim3(64 * NW), 0, s, P, items,
+                         static_cast<const ST*>(bank), static_cast<const ST*>(fdl), sel, ypart, counter);
+      return hipGetLastError();
+    });
+  });
 }
 
-hipError_t launch_inv(const DevPlan& P, int tile_width, const float2* ypart, const int32_t* rows_ptr,
-                      const int32_t* rows, float* ola, float* out, int64_t out_stride, const int32_t* sel_in,
-                      int32_t* sel_store, uint64_t* counter, hipStream_t s) {
-  switch (P.L) {
-    case 64: return inv_l<64>(P, tile_width, ypart, rows_ptr, rows, ola, out, out_stride, sel_in, sel_store, counter, s);
-    case 128: return inv_l<128>(P, tile_width, ypart, rows_ptr, rows, ola, out, out_stride, sel_in, sel_store, counter, s);
-    case 256: return inv_l<256>(P, tile_width, ypart, rows_ptr, rows, ola, out, out_stride, sel_in, sel_store, counter, s);
-    case 512: return inv_l<512>(P, tile_width, ypart, rows_ptr, rows, ola, out, out_stride, sel_in, sel_store, counter, s);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_inv(const DevPlan& P, int dtype, const float2* ypart, const void* bank, const void* fdl,
+                      const int32_t* sel, float* ola, float* out, int64_t out_stride, int32_t copy_sel,
+                      int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s) {
+  return by_hop(P.L, [&](auto Lc) {
+    return by_dtype(dtype, [&](auto Dc) {
+      constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value;
+      using ST = typename Store<DT>::T;
+      hipLaunchKernelGGL((k_inv<L, DT>), dim3(P.C), dim3(64), 0, s, P, ypart, static_cast<const ST*>(bank),
+                         static_cast<const ST*>(fdl), sel, ola, out, out_stride, copy_sel, sel_store, done, counter);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s) {
+  if (A.n_items <= 0 || grid <= 0) return hipErrorInvalidValue;
+  return by_hop(A.P.L, [&](auto Lc) {
+    return by_dtype(dtype, [&](auto Dc) {
+      return by_shape(shape, [&](auto Vc, auto Gc, auto NWc) {
+        constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value, V = decltype(Vc)::value,
+                      G = decltype(Gc)::value, NW = decltype(NWc)::value;
+        if constexpr (64 * V > 2 * L) {
+          return hipErrorInvalidValue;
+        } else {
+          hipLaunchKernelGGL((k_block<L, V, G, NW, DT>), dim3(grid), dim3(64 * NW), 0, s, A);
+          return hipGetLastError();
+        }
+      });
+    });
+  });
 }
 
 hipError_t launch_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M, void* dst,
                          hipStream_t s) {
-  switch (dtype) {
-    case 0: return irprep_dt<0>(P, taps, n_taps, M, dst, s);
-    case 1: return irprep_dt<1>(P, taps, n_taps, M, dst, s);
-    case 2: return irprep_dt<2>(P, taps, n_taps, M, dst, s);
-    default: return hipErrorInvalidValue;
-  }
+  return by_hop(P.L, [&](auto Lc) {
+    return by_dtype(dtype, [&](auto Dc) {
+      constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value;
+      hipLaunchKernelGGL((k_irprep<L, DT>), dim3(M), dim3(64), 0, s, P, taps, n_taps,
+                         static_cast<typename Store<DT>::T*>(dst));
+      return hipGetLastError();
+    });
+  });
 }
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {

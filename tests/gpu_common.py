@@ -40,26 +40,39 @@ def oracle_streams(wl, channels=None, dtype: str = "f32") -> np.ndarray:
     return out
 
 
-def make_convolver(wl, dtype: str = "f32", stream=None):
+MODES = {
+    "fused": dict(fused=1),
+    "plain": dict(fused=0),
+    "two_kernel": dict(fused=2),
+    "persistent": dict(fused=1, grid=7),
+    "tiny_chunks": dict(fused=1, chunk=2, waves=8),
+    "two_kernel_tiny": dict(fused=2, chunk=3, waves=8, grid=5),
+    "plain_tiny_chunks": dict(fused=0, chunk=3, waves=8),
+}
+
+
+def make_convolver(wl, dtype: str = "f32", stream=None, mode: str = "fused"):
     from paper_2310_00319_amd import Convolver
 
     conv = Convolver(hop=wl.hop, n_channels=wl.n_channels, max_taps=wl.max_taps(),
                      n_inputs=wl.n_inputs, input_of_channel=wl.input_of_channel,
                      taps_of_channel=wl.taps_of_channel, n_slots=wl.n_slots, dtype=dtype, stream=stream)
+    if mode != "fused":
+        conv.configure(**MODES[mode])
     for c in range(wl.n_channels):
         for s in range(wl.n_slots):
             conv.set_ir(c, s, wl.taps[c][s])
     return conv
 
 
-def gpu_streams(wl, dtype: str = "f32", conv=None):
+def gpu_streams(wl, dtype: str = "f32", conv=None, mode: str = "fused"):
     """Whole workload through the library with a device-resident schedule.
     Returns the [C][n_calls*L] output as float64 numpy."""
     import torch
 
     own = conv is None
     if own:
-        conv = make_convolver(wl, dtype)
+        conv = make_convolver(wl, dtype, mode=mode)
     x = torch.from_numpy(wl.padded_input()).cuda()
     sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
     out = conv.process(x, sched)

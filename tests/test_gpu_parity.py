@@ -28,8 +28,8 @@ def _gpu():
     yield
 
 
-def _check(wl, dtype="f32", channels=None, tol=TOL_F32, name=""):
-    got = gpu_streams(wl, dtype)
+def _check(wl, dtype="f32", channels=None, tol=TOL_F32, name="", mode="fused"):
+    got = gpu_streams(wl, dtype, mode=mode)
     chans = list(range(wl.n_channels)) if channels is None else list(channels)
     ref = oracle_streams(wl, chans)
     err = rel_rms_per_channel(got[chans], ref)
@@ -67,13 +67,57 @@ SMALL_CASES = [
 ]
 
 
+@pytest.mark.parametrize("mode", ["fused", "plain", "two_kernel", "persistent", "tiny_chunks", "two_kernel_tiny",
+                                  "plain_tiny_chunks"])
 @pytest.mark.parametrize("case", SMALL_CASES, ids=[f"s{c[0]}_L{c[1]}" for c in SMALL_CASES])
-def test_stream_parity_small(case):
+def test_stream_parity_small(case, mode):
     seed, L, C, I, N, tr, K, p = case
-    log(f"small case {case}")
+    log(f"small case {case} mode {mode}")
     wl = synth.random_small(seed=seed, hop=L, n_channels=C, n_inputs=I, n_samples=N,
                             taps_range=tr, n_slots=K, p_switch=p)
-    _check(wl, name=f"small{seed}")
+    _check(wl, name=f"small{seed}-{mode}", mode=mode)
+
+
+def test_autotune_then_parity():
+    log("autotune")
+    wl = synth.random_small(seed=31, hop=128, n_channels=8, n_inputs=4, n_samples=128 * 30,
+                            taps_range=(1000, 20000), n_slots=2, p_switch=0.3)
+    conv = make_convolver(wl)
+    best = conv.autotune(iters=3)
+    info = conv.info()
+    log(f"autotune best {best:.2f} us/block; choice chunk={info['mac_chunk']} waves={info['mac_waves']} "
+        f"grid={info['mac_grid']} items={info['n_work_items']}")
+    got = gpu_streams(wl, conv=conv)
+    conv.close()
+    ref = oracle_streams(wl)
+    assert rel_rms_per_channel(got, ref).max() <= TOL_F32
+
+
+def test_graph_capture_replays_match_eager():
+    import torch
+    log("graph capture")
+    wl = synth.random_small(seed=32, hop=64, n_channels=6, n_inputs=3, n_samples=64 * 20,
+                            taps_range=(200, 2000), n_slots=3, p_switch=0.5)
+    eager = gpu_streams(wl).astype(np.float32)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        conv = make_convolver(wl, stream=stream)
+        x = torch.from_numpy(wl.padded_input()).cuda()
+        sched = torch.from_numpy(wl.schedule.astype(np.int32)).cuda()
+        out = torch.zeros((wl.n_channels, wl.n_calls * wl.hop), device="cuda")
+        stream.synchronize()
+        conv.capture_begin()
+        conv.process(x, sched, out)
+        conv.capture_end()
+        for rep in range(3):
+            out.zero_()
+            conv.reset()
+            conv.graph_launch()
+            stream.synchronize()
+            got = out.cpu().numpy()
+            assert np.array_equal(got, eager), f"replay {rep} differs"
+            _ = (torch.randn(1000, device="cuda") * 2).sum().item()   # unrelated eager work between replays
+        conv.close()
 
 
 @pytest.mark.parametrize("dtype,min_snr_db", [("bf16", 40.0), ("f16", 58.0)])
