@@ -178,7 +178,7 @@ __device__ __forceinline__ void input_spectrum(const DevPlan& P, const float* __
 // acc[g] += H_{c_g, slot}(m) X(l - 2m) for this lane's V bins. The waves of the
 // workgroup take every NW-th partition; two partitions are in flight per wave.
 // The packed bin 0 holds two real bins and multiplies component-wise.
-template <int V, int G, int NW, int DT>
+template <int V, int G, int NW, int DT, int U>
 __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
                                          const typename Store<DT>::T* __restrict__ bank,
                                          const typename Store<DT>::T* __restrict__ fdl,
@@ -190,8 +190,9 @@ __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
   const int Mi = P.in_M[it.input];
   const int q = ring_slot(cnt, Mi);
   const int kbase = it.tile * TW + lane * V;
-  const ST* xrow = fdl + P.in_fdl_off[it.input] + (int64_t)p * Mi * N + kbase;
-  const ST* hrow[G];
+  // Row bases are uniform across the wave; lanes add a 32-bit offset.
+  const ST* xbase = fdl + P.in_fdl_off[it.input] + (int64_t)p * Mi * N;
+  const ST* hbase[G];
   int Mc[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -200,10 +201,10 @@ __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
       int s = sel[ch];
       s = s < 0 ? 0 : (s >= P.K ? P.K - 1 : s);
       Mc[g] = P.ch_M[ch];
-      hrow[g] = bank + P.ch_bank_off[ch] + (int64_t)s * Mc[g] * N + kbase;
+      hbase[g] = bank + P.ch_bank_off[ch] + (int64_t)s * Mc[g] * N;
     } else {
       Mc[g] = 0;
-      hrow[g] = bank;
+      hbase[g] = bank;
     }
   }
   const bool dc_lane = (kbase == 0);
@@ -221,37 +222,36 @@ __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
     }
   };
   int m = (it.m0 > 1 ? it.m0 : 1) + w;
-  for (; m + NW < it.m1; m += 2 * NW) {
-    const int m2 = m + NW;
-    int xr1 = q - m;
-    if (xr1 < 0) xr1 += Mi;
-    int xr2 = q - m2;
-    if (xr2 < 0) xr2 += Mi;
-    float2 X1[V], X2[V];
-    float2 H1[G][V], H2[G][V];
-    load_vec<DT, V>(xrow + (int64_t)xr1 * N, X1);
-    load_vec<DT, V>(xrow + (int64_t)xr2 * N, X2);
+  for (; m + (U - 1) * NW < it.m1; m += U * NW) {
+    float2 X[U][V];
+    float2 H[U][G][V];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      if (m < Mc[g]) load_vec<DT, V>(hrow[g] + (int64_t)m * N, H1[g]);
-      if (m2 < Mc[g]) load_vec<DT, V>(hrow[g] + (int64_t)m2 * N, H2[g]);
+    for (int u = 0; u < U; ++u) {
+      int xr = q - (m + u * NW);
+      if (xr < 0) xr += Mi;
+      load_vec<DT, V>(xbase + (uint32_t)(xr * N + kbase), X[u]);
     }
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      if (m < Mc[g]) accumulate(g, H1[g], X1);
-      if (m2 < Mc[g]) accumulate(g, H2[g], X2);
-    }
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (m + u * NW < Mc[g]) load_vec<DT, V>(hbase[g] + (uint32_t)((m + u * NW) * N + kbase), H[u][g]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (m + u * NW < Mc[g]) accumulate(g, H[u][g], X[u]);
   }
-  if (m < it.m1) {
+  for (; m < it.m1; m += NW) {
     int xr = q - m;
     if (xr < 0) xr += Mi;
     float2 X[V];
-    load_vec<DT, V>(xrow + (int64_t)xr * N, X);
+    load_vec<DT, V>(xbase + (uint32_t)(xr * N + kbase), X);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (m < Mc[g]) {
         float2 H[V];
-        load_vec<DT, V>(hrow[g] + (int64_t)m * N, H);
+        load_vec<DT, V>(hbase[g] + (uint32_t)(m * N + kbase), H);
         accumulate(g, H, X);
       }
     }
@@ -285,16 +285,21 @@ __device__ __forceinline__ void write_partials(const WorkItem& it, float2 (&acc)
 // out(n) = state(n) + y(n) for n < L, state'(n) = state(n + L) + y(n + L) for
 // n < 2L, state'(2L + n) = y(3L + n) for n < L. Y, bufA, bufB in LDS.
 template <int L, int T>
-__device__ __forceinline__ void inverse_ola(float2* Y, float2* bufA, float2* bufB, const float2* twl,
-                                            float* __restrict__ st, float* __restrict__ o, int tid) {
-  constexpr int N = 2 * L;
-  constexpr int NPT = (4 * L + T - 1) / T;
-  float old[NPT];
+__device__ __forceinline__ void ola_prefetch(const float* __restrict__ st, float (&old)[(4 * L + T - 1) / T],
+                                             int tid) {
 #pragma unroll
-  for (int j = 0; j < NPT; ++j) {
+  for (int j = 0; j < (4 * L + T - 1) / T; ++j) {
     const int n = tid + j * T;
     old[j] = (n < 3 * L) ? st[n] : 0.f;
   }
+}
+
+template <int L, int T>
+__device__ __forceinline__ void inverse_ola(float2* Y, float2* bufA, float2* bufB, const float2* twl,
+                                            const float (&old)[(4 * L + T - 1) / T], float* __restrict__ st,
+                                            float* __restrict__ o, int tid) {
+  constexpr int N = 2 * L;
+  constexpr int NPT = (4 * L + T - 1) / T;
 #pragma unroll
   for (int k = tid; k < N; k += T) bufA[k] = fft::real_inv_pre_conj<N>(Y, k, twl);
   __syncthreads();
@@ -340,6 +345,9 @@ __device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __
   int s = sel[c];
   s = s < 0 ? 0 : (s >= P.K ? P.K - 1 : s);
   const ST* h0 = bank + P.ch_bank_off[c] + (int64_t)s * P.ch_M[c] * N;
+  float* st = ola + (int64_t)c * 3 * L;
+  float old[(4 * L + T - 1) / T];
+  ola_prefetch<L, T>(st, old, tid);    // in flight together with the loads below
 #pragma unroll
   for (int k = tid; k < N; k += T) {
     const float2 X = unpack<DT>(load_maybe<COHERENT>(xrow + k));
@@ -361,7 +369,7 @@ __device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __
     Y[k] = cadd(cadd(s0, s1), cadd(s2, s3));
   }
   __syncthreads();
-  inverse_ola<L, T>(Y, bufA, bufB, twl, ola + (int64_t)c * 3 * L, out + (int64_t)c * out_stride, tid);
+  inverse_ola<L, T>(Y, bufA, bufB, twl, old, st, out + (int64_t)c * out_stride, tid);
 }
 
 // ---------------------------------------------------------------- fused per-block kernel
@@ -392,7 +400,10 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
   const ST* bank = static_cast<const ST*>(A.bank);
   ST* fdl = static_cast<ST*>(A.fdl);
   const bool inl = A.inverse_inline != 0;
-  bool tables = false;
+  // The FFT tables are loaded up front (made visible by the first barrier), so
+  // neither spectrum items nor channel completions wait for them later.
+  load_tables<L, T>(P, twl, winl, tid);
+  bool tables = true;
 
   // Count one arrival for channel c; if it was the last one, complete c.
   auto arrive = [&](int c) {
@@ -435,7 +446,10 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
       }
     } else {
       float2 acc[G][V];
-      mac_item<V, G, NW, DT>(P, it, bank, fdl, A.sel, p, cnt, lane, w, acc);
+      // two partitions in flight per wave keep the fused kernel within 128
+      // VGPRs, so two 8-wave workgroups (e.g. a spectrum item next to a MAC
+      // item) fit on one compute unit
+      mac_item<V, G, NW, DT, 2>(P, it, bank, fdl, A.sel, p, cnt, lane, w, acc);
       if (inl) {
         write_partials<V, G, NW, true>(it, acc, red, A.ypart, lane, w, tid);
         wait_memory();
@@ -490,7 +504,7 @@ __global__ __launch_bounds__(64 * NW) void k_mac(DevPlan P, const WorkItem* __re
   const int tid = threadIdx.x;
   const uint64_t cnt = *counter;
   float2 acc[G][V];
-  mac_item<V, G, NW, DT>(P, it, bank, fdl, sel, (int)(cnt & 1u), cnt, tid & 63, tid >> 6, acc);
+  mac_item<V, G, NW, DT, (G * V <= 4) ? 4 : 2>(P, it, bank, fdl, sel, (int)(cnt & 1u), cnt, tid & 63, tid >> 6, acc);
   write_partials<V, G, NW, false>(it, acc, red, ypart, tid & 63, tid >> 6, tid);
 }
 
