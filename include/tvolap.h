@@ -189,6 +189,55 @@ int tvolap_set_timing(tvolap_t* h, int32_t enable);
 int tvolap_get_timing(tvolap_t* h, double* ms_in, double* ms_mac, double* ms_out,
                       int64_t* n_blocks);
 
+/* ------------------------------------------------------------------------
+ * Offline, differentiable form. A whole signal per channel is processed at
+ * once: channel c filters x[c][0 .. N) with its K partition-spectrum sets
+ * H[c][s][m][k] (k = 0 .. 2L, complex float32 interleaved re/im, the paper's
+ * H(k, m) of eq. 6) under schedule[b][c], the set active at block b (b = 0 ..
+ * nblk-1 with nblk = ceil(N/L) + 1; block b is the paper's block l = b - 1,
+ * covering samples [(b-1)L, (b+1)L)); NULL schedule = set 0 throughout. The
+ * output y[c][0 .. N) is the time-variant convolution of Sec. 2 (equal to the
+ * streaming output without its L-sample delay). Imaginary parts of H at
+ * k = 0 and k = 2L do not enter (the inverse transform of eq. 9 is real).
+ * All arrays are device memory; work is enqueued on `stream` (hipStream_t,
+ * NULL = null stream) and the calls return without waiting. The caller
+ * provides a device workspace of tvolap_offline_workspace_bytes() bytes,
+ * which the call may overwrite; it is not used after the call's work ends.
+ * Errors: EINVAL (shape, NULL pointer, small workspace), EDEVICE; the message
+ * is in tvolap_offline_last_error(). */
+typedef struct {
+  int32_t hop;            /* L: 64, 128, 256 or 512                         */
+  int32_t n_channels;     /* C, 1 .. 65535                                  */
+  int32_t n_partitions;   /* M >= 1                                         */
+  int32_t n_slots;        /* K >= 1                                         */
+  int64_t n_samples;      /* N >= 1                                         */
+} tvolap_offline_shape;
+
+/* Workspace size in bytes, or -1 for an invalid shape. */
+int64_t tvolap_offline_workspace_bytes(const tvolap_offline_shape* shape);
+
+/* H[c][s][m][k] (k = 0 .. 2L) of taps[c][s][0 .. n_taps): partition m holds
+ * taps [2Lm, 2Lm + 2L), zero padded to 4L and transformed (eq. 3, 6-7).
+ * n_taps in [1, 2LM]. */
+int tvolap_offline_ir_spectra(const tvolap_offline_shape* shape, const float* taps, int32_t n_taps, float* H,
+                              void* stream);
+
+/* y = TVOLAP(x, H, schedule) (eq. 1-13). */
+int tvolap_offline_forward(const tvolap_offline_shape* shape, const float* x, const float* H,
+                           const int32_t* schedule, float* y, void* workspace, int64_t workspace_bytes,
+                           void* stream);
+
+/* Adjoint of the forward map for a real loss with gradient gy = dLoss/dy
+ * ([C][N]): dx[c][t] = dLoss/dx[c][t] and dH[c][s][m][k] = dLoss/dRe H +
+ * i dLoss/dIm H (zero imaginary parts at k = 0 and 2L). Either output may be
+ * NULL to skip it. The input spectra are recomputed from x. */
+int tvolap_offline_backward(const tvolap_offline_shape* shape, const float* x, const float* H,
+                            const int32_t* schedule, const float* gy, float* dx, float* dH, void* workspace,
+                            int64_t workspace_bytes, void* stream);
+
+/* Message describing the last failed offline call of this thread. */
+const char* tvolap_offline_last_error(void);
+
 /* Message describing the last error of `h`, or of the last failed
  * tvolap_create when h is NULL. Never NULL. */
 const char* tvolap_last_error(const tvolap_t* h);

@@ -5,5 +5,6 @@ The compute path is the gfx950 HIP library ``libtvolap.so`` (C ABI in
 """
 from .convolver import Convolver  # noqa: F401
 from ._lib import TvolapError, load  # noqa: F401
+from . import functional  # noqa: F401
 
-__all__ = ["Convolver", "TvolapError", "load"]
+__all__ = ["Convolver", "TvolapError", "load", "functional"]

@@ -30,8 +30,19 @@ EXPORTED = (
     "tvolap_process_block", "tvolap_reset", "tvolap_get_info", "tvolap_get_partitions",
     "tvolap_set_timing", "tvolap_get_timing", "tvolap_last_error", "tvolap_version",
     "tvolap_configure", "tvolap_autotune", "tvolap_capture_begin", "tvolap_capture_end",
-    "tvolap_graph_launch",
+    "tvolap_graph_launch", "tvolap_offline_workspace_bytes", "tvolap_offline_ir_spectra",
+    "tvolap_offline_forward", "tvolap_offline_backward", "tvolap_offline_last_error",
 )
+
+
+class TvolapOfflineShape(ctypes.Structure):
+    _fields_ = [
+        ("hop", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("n_partitions", ctypes.c_int32),
+        ("n_slots", ctypes.c_int32),
+        ("n_samples", ctypes.c_int64),
+    ]
 
 
 class TvolapConfig(ctypes.Structure):
@@ -116,11 +127,20 @@ def _declare(lib):
     lib.tvolap_graph_launch.argtypes = [c_vp]
     lib.tvolap_version.argtypes = []
     lib.tvolap_version.restype = ctypes.c_char_p
+    shp = ctypes.POINTER(TvolapOfflineShape)
+    lib.tvolap_offline_workspace_bytes.argtypes = [shp]
+    lib.tvolap_offline_workspace_bytes.restype = c_i64
+    lib.tvolap_offline_ir_spectra.argtypes = [shp, c_vp, c_i32, c_vp, c_vp]
+    lib.tvolap_offline_forward.argtypes = [shp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]
+    lib.tvolap_offline_backward.argtypes = [shp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]
+    lib.tvolap_offline_last_error.argtypes = []
+    lib.tvolap_offline_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         fn = getattr(lib, name)
-        if fn.restype is None or fn.restype is ctypes.c_int:
-            if name not in ("tvolap_last_error", "tvolap_version"):
-                fn.restype = c_int
+        if name in ("tvolap_last_error", "tvolap_version", "tvolap_offline_last_error",
+                    "tvolap_offline_workspace_bytes"):
+            continue
+        fn.restype = c_int
 
 
 def load():
@@ -141,6 +161,11 @@ def load():
     _declare(lib)
     _lib = lib
     return lib
+
+
+def check_offline(code: int):
+    if code != TVOLAP_OK:
+        raise TvolapError(code, load().tvolap_offline_last_error().decode(errors="replace"))
 
 
 def check(code: int, handle=None):

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtvolap.so")
-SOURCES = ["tvolap_kernels.hip", "tvolap_capi.cpp"]
+SOURCES = ["tvolap_kernels.hip", "tvolap_offline.hip", "tvolap_capi.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

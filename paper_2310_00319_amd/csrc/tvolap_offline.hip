@@ -1,0 +1,467 @@
+// Offline (whole-signal) TVOLAP and its adjoint on gfx950 (Sec. 2 of Jaeger et
+// al., arXiv 2310.00319, read as a linear map from (x, H) to y).
+//
+// Block b (b = 0 .. nblk-1) is the paper's block l = b - 1: it covers input
+// samples [(b-1)L, (b+1)L) and its 4L-sample output lands at (b-1)L. Spectra
+// are kept packed (2L complex values, slot 0 = (Re X(0), Re X(2L))).
+//
+// Forward:  X_b = DFT_4L(w . x_b)                         (eq. 1, 2, 4, 5)
+//           Y_b = sum_m H_{g(b)}(m) X_{b-2m}                (eq. 8)
+//           y   = overlap-add of IDFT_4L(Y_b) at hop L      (eq. 9-13)
+// Adjoint (real loss, gradients written as dL/dRe + i dL/dIm):
+//           G_b   = (c_k / 4L) DFT_4L(gy_b), c_k = 1 at k = 0, 2L, else 2
+//           dH_s(m) = sum_{b: g(b) = s} G_b conj(X_{b-2m})
+//           dX_j    = sum_m G_{j+2m} conj(H_{g(j+2m)}(m))
+//           dxhat_j(n) = sum_{k <= 2L} Re(dX_j(k) e^{+i 2 pi n k / 4L}), n < 2L
+//           dx(t)   = sum_j w(t - jL') dxhat_j(t - jL')     (windowed overlap-add)
+// The input spectra X are recomputed from x in the backward pass instead of
+// being kept from the forward pass.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "../../include/tvolap.h"
+#include "fft_lds.hpp"
+
+namespace tvx {
+namespace off {
+namespace {
+
+using fft::cadd;
+using fft::cconj;
+using fft::cmul;
+using fft::cscale;
+
+constexpr int T = 256;   // threads per workgroup of the per-block kernels
+
+struct Shape {
+  int32_t L, C, K, M, nblk;
+  int64_t N;
+};
+
+// Twiddles exp(-2 pi i t / 4L) and the window (1 - cos(2 pi n / 2L)) / 2,
+// evaluated in double precision and rounded to float, into LDS.
+template <int L>
+__device__ __forceinline__ void make_tables(float2* twl, float* winl, int tid) {
+  for (int t = tid; t < 4 * L; t += T) {
+    double sn, cs;
+    sincospi(-(double)t / (double)(2 * L), &sn, &cs);
+    twl[t] = make_float2((float)cs, (float)sn);
+  }
+  if (winl)
+    for (int n = tid; n < 2 * L; n += T) winl[n] = (float)(0.5 * (1.0 - cospi((double)n / (double)L)));
+}
+
+// packed product; bin 0 carries two real bins and multiplies component-wise
+__device__ __forceinline__ float2 pmul(float2 a, float2 b, bool dc) {
+  return dc ? make_float2(a.x * b.x, a.y * b.y) : cmul(a, b);
+}
+// packed product with the conjugate of b
+__device__ __forceinline__ float2 pmulc(float2 a, float2 b, bool dc) {
+  return dc ? make_float2(a.x * b.x, a.y * b.y) : cmul(a, cconj(b));
+}
+
+__device__ __forceinline__ int slot_of(const int32_t* sched, int b, int c, int C, int K) {
+  if (!sched) return 0;
+  int s = sched[(int64_t)b * C + c];
+  return s < 0 ? 0 : (s >= K ? K - 1 : s);
+}
+
+// H [C][K][M][2L+1] complex -> packed Hp [C][K][M][2L]
+__global__ __launch_bounds__(T) void k_pack(Shape S, const float2* __restrict__ H, float2* __restrict__ Hp) {
+  const int N = 2 * S.L;
+  const int64_t row = blockIdx.x;   // (c, s, m)
+  const float2* src = H + row * (N + 1);
+  float2* dst = Hp + row * N;
+  for (int k = threadIdx.x; k < N; k += T)
+    dst[k] = (k == 0) ? make_float2(src[0].x, src[N].x) : src[k];
+}
+
+// X_all[c][b] = packed spectrum of the windowed block b of x[c]
+template <int L>
+__global__ __launch_bounds__(T) void k_spectra(Shape S, const float* __restrict__ x, float2* __restrict__ Xall) {
+  constexpr int N = 2 * L;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  const int b = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  make_tables<L>(twl, winl, tid);
+  __syncthreads();
+  const float* xc = x + (int64_t)c * S.N;
+  const int64_t t0 = (int64_t)(b - 1) * L;
+  for (int n = tid; n < L; n += T) {
+    const int64_t ta = t0 + 2 * n, tb = ta + 1;
+    const float s0 = (ta >= 0 && ta < S.N) ? xc[ta] : 0.f;
+    const float s1 = (tb >= 0 && tb < S.N) ? xc[tb] : 0.f;
+    bufA[n] = make_float2(winl[2 * n] * s0, winl[2 * n + 1] * s1);
+    bufA[n + L] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const float2* Z = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  float2* dst = Xall + ((int64_t)c * S.nblk + b) * N;
+  for (int k = tid; k < N; k += T) dst[k] = fft::real_fwd_post<N>(Z, k, twl);
+}
+
+// y_b = IDFT_4L(sum_m H_{g(b)}(m) X_{b-2m}) -> yb[c][b][4L]
+template <int L>
+__global__ __launch_bounds__(T) void k_fwd_blocks(Shape S, const float2* __restrict__ Hp,
+                                                  const float2* __restrict__ Xall, const int32_t* __restrict__ sched,
+                                                  float* __restrict__ yb) {
+  constexpr int N = 2 * L;
+  __shared__ float2 twl[2 * N];
+  __shared__ float2 Y[N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  const int b = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  make_tables<L>(twl, nullptr, tid);
+  const int s = slot_of(sched, b, c, S.C, S.K);
+  const float2* H = Hp + (((int64_t)c * S.K + s) * S.M) * N;
+  const float2* X = Xall + (int64_t)c * S.nblk * N;
+  for (int k = tid; k < N; k += T) {
+    float2 acc = make_float2(0.f, 0.f);
+    for (int m = 0; m < S.M && b - 2 * m >= 0; ++m)
+      acc = cadd(acc, pmul(H[(int64_t)m * N + k], X[(int64_t)(b - 2 * m) * N + k], k == 0));
+    Y[k] = acc;
+  }
+  __syncthreads();
+  for (int k = tid; k < N; k += T) bufA[k] = fft::real_inv_pre_conj<N>(Y, k, twl);
+  __syncthreads();
+  const float2* R = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  constexpr float scale = 1.0f / (float)(4 * L);
+  float* dst = yb + ((int64_t)c * S.nblk + b) * 4 * L;
+  for (int n = tid; n < 4 * L; n += T) {
+    const float2 z = R[n >> 1];
+    dst[n] = ((n & 1) ? -z.y : z.x) * scale;
+  }
+}
+
+// y[c][t] = sum over the (up to four) blocks whose output covers t
+__global__ __launch_bounds__(T) void k_ola(Shape S, const float* __restrict__ yb, float* __restrict__ y) {
+  const int c = blockIdx.y;
+  const int L = S.L;
+  for (int64_t t = (int64_t)blockIdx.x * T + threadIdx.x; t < S.N; t += (int64_t)gridDim.x * T) {
+    const int64_t q = t / L;
+    float acc = 0.f;
+    for (int64_t b = q - 2; b <= q + 1; ++b) {
+      if (b < 0 || b >= S.nblk) continue;
+      const int64_t off = t - (b - 1) * L;
+      if (off >= 0 && off < 4 * L) acc += yb[((int64_t)c * S.nblk + b) * 4 * L + off];
+    }
+    y[(int64_t)c * S.N + t] = acc;
+  }
+}
+
+// G_b = (c_k / 4L) DFT_4L(gy over [(b-1)L, (b+3)L)) -> gspec[c][b][2L] (packed)
+template <int L>
+__global__ __launch_bounds__(T) void k_gspec(Shape S, const float* __restrict__ gy, float2* __restrict__ gspec) {
+  constexpr int N = 2 * L;
+  __shared__ float2 twl[2 * N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  const int b = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  make_tables<L>(twl, nullptr, tid);
+  const float* g = gy + (int64_t)c * S.N;
+  const int64_t t0 = (int64_t)(b - 1) * L;
+  for (int n = tid; n < N; n += T) {
+    const int64_t ta = t0 + 2 * n, tb = ta + 1;
+    bufA[n] = make_float2((ta >= 0 && ta < S.N) ? g[ta] : 0.f, (tb >= 0 && tb < S.N) ? g[tb] : 0.f);
+  }
+  __syncthreads();
+  const float2* Z = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  constexpr float end = 1.0f / (float)(4 * L);
+  constexpr float mid = 2.0f / (float)(4 * L);
+  float2* dst = gspec + ((int64_t)c * S.nblk + b) * N;
+  for (int k = tid; k < N; k += T) dst[k] = cscale(fft::real_fwd_post<N>(Z, k, twl), k == 0 ? end : mid);
+}
+
+// dH[c][s][m][k] = sum_{b: g(b)=s, b-2m >= 0} G_b(k) conj(X_{b-2m}(k)), written unpacked ([2L+1] bins)
+__global__ __launch_bounds__(T) void k_dH(Shape S, const float2* __restrict__ gspec, const float2* __restrict__ Xall,
+                                          const int32_t* __restrict__ sched, float2* __restrict__ dH) {
+  const int N = 2 * S.L;
+  const int64_t row = blockIdx.x;                    // (c, s, m)
+  const int m = (int)(row % S.M);
+  const int s = (int)((row / S.M) % S.K);
+  const int c = (int)(row / ((int64_t)S.M * S.K));
+  const float2* G = gspec + (int64_t)c * S.nblk * N;
+  const float2* X = Xall + (int64_t)c * S.nblk * N;
+  float2* dst = dH + row * (N + 1);
+  for (int k = threadIdx.x; k < N; k += T) {
+    float2 acc = make_float2(0.f, 0.f);
+    for (int b = 2 * m; b < S.nblk; ++b) {
+      if (slot_of(sched, b, c, S.C, S.K) != s) continue;
+      acc = cadd(acc, pmulc(G[(int64_t)b * N + k], X[(int64_t)(b - 2 * m) * N + k], k == 0));
+    }
+    if (k == 0) {
+      dst[0] = make_float2(acc.x, 0.f);
+      dst[N] = make_float2(acc.y, 0.f);
+    } else {
+      dst[k] = acc;
+    }
+  }
+}
+
+// dxhat_j = w . (first 2L samples of the R2C adjoint of dX_j) -> dxb[c][j][2L]
+template <int L>
+__global__ __launch_bounds__(T) void k_dx_blocks(Shape S, const float2* __restrict__ gspec,
+                                                 const float2* __restrict__ Hp, const int32_t* __restrict__ sched,
+                                                 float* __restrict__ dxb) {
+  constexpr int N = 2 * L;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
+  __shared__ float2 D[N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  const int j = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  make_tables<L>(twl, winl, tid);
+  const float2* G = gspec + (int64_t)c * S.nblk * N;
+  for (int k = tid; k < N; k += T) {
+    float2 acc = make_float2(0.f, 0.f);
+    for (int m = 0; m < S.M && j + 2 * m < S.nblk; ++m) {
+      const int b = j + 2 * m;
+      const int s = slot_of(sched, b, c, S.C, S.K);
+      const float2* H = Hp + (((int64_t)c * S.K + s) * S.M + m) * N;
+      acc = cadd(acc, pmulc(G[(int64_t)b * N + k], H[k], k == 0));
+    }
+    // sum_k Re(D(k) e^{+i theta}) over the 2L + 1 bins equals the normalised
+    // inverse real DFT of D scaled by 4L at k = 0, 2L and by 2L elsewhere
+    D[k] = (k == 0) ? cscale(acc, (float)(4 * L)) : cscale(acc, (float)(2 * L));
+  }
+  __syncthreads();
+  for (int k = tid; k < N; k += T) bufA[k] = fft::real_inv_pre_conj<N>(D, k, twl);
+  __syncthreads();
+  const float2* R = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  constexpr float scale = 1.0f / (float)(4 * L);
+  float* dst = dxb + ((int64_t)c * S.nblk + j) * N;
+  for (int n = tid; n < N; n += T) {
+    const float2 z = R[n >> 1];
+    dst[n] = winl[n] * ((n & 1) ? -z.y : z.x) * scale;
+  }
+}
+
+// dx[c][t] = sum of the two windowed blocks that cover t
+__global__ __launch_bounds__(T) void k_dx_ola(Shape S, const float* __restrict__ dxb, float* __restrict__ dx) {
+  const int c = blockIdx.y;
+  const int L = S.L;
+  const int N = 2 * L;
+  for (int64_t t = (int64_t)blockIdx.x * T + threadIdx.x; t < S.N; t += (int64_t)gridDim.x * T) {
+    const int64_t q = t / L;
+    float acc = 0.f;
+    for (int64_t j = q; j <= q + 1; ++j) {
+      if (j < 0 || j >= S.nblk) continue;
+      const int64_t off = t - (j - 1) * L;
+      if (off >= 0 && off < N) acc += dxb[((int64_t)c * S.nblk + j) * N + off];
+    }
+    dx[(int64_t)c * S.N + t] = acc;
+  }
+}
+
+// IR spectra for the offline path: taps [C][K][n_taps] -> H [C][K][M][2L+1]
+template <int L>
+__global__ __launch_bounds__(T) void k_ir_spectra(Shape S, const float* __restrict__ taps, int32_t n_taps,
+                                                  float2* __restrict__ H) {
+  constexpr int N = 2 * L;
+  __shared__ float2 twl[2 * N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  const int64_t row = blockIdx.x;     // (c, s, m)
+  const int m = (int)(row % S.M);
+  const int64_t cs = row / S.M;
+  const int tid = threadIdx.x;
+  make_tables<L>(twl, nullptr, tid);
+  const float* h = taps + cs * n_taps;
+  for (int n = tid; n < L; n += T) {
+    const int t0 = N * m + 2 * n;
+    bufA[n] = make_float2(t0 < n_taps ? h[t0] : 0.f, t0 + 1 < n_taps ? h[t0 + 1] : 0.f);
+    bufA[n + L] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const float2* Z = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  float2* dst = H + row * (N + 1);
+  for (int k = tid; k < N; k += T) {
+    const float2 v = fft::real_fwd_post<N>(Z, k, twl);
+    if (k == 0) {
+      dst[0] = make_float2(v.x, 0.f);
+      dst[N] = make_float2(v.y, 0.f);
+    } else {
+      dst[k] = v;
+    }
+  }
+}
+
+template <typename F>
+hipError_t by_hop(int L, F&& f) {
+  switch (L) {
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 128: return f(std::integral_constant<int, 128>{});
+    case 256: return f(std::integral_constant<int, 256>{});
+    case 512: return f(std::integral_constant<int, 512>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+struct Workspace {
+  float2* Hp;      // [C][K][M][2L]
+  float2* Xall;    // [C][nblk][2L]
+  float* blk;      // [C][nblk][4L] (forward output blocks / gradient spectra)
+};
+
+int64_t align_up(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+int64_t workspace_layout(const Shape& S, Workspace* w, char* base) {
+  const int N = 2 * S.L;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const int64_t o_hp = take((int64_t)S.C * S.K * S.M * N * 8);
+  const int64_t o_x = take((int64_t)S.C * S.nblk * N * 8);
+  const int64_t o_b = take((int64_t)S.C * S.nblk * 4 * S.L * 4);
+  if (w && base) {
+    w->Hp = reinterpret_cast<float2*>(base + o_hp);
+    w->Xall = reinterpret_cast<float2*>(base + o_x);
+    w->blk = reinterpret_cast<float*>(base + o_b);
+  }
+  return off;
+}
+
+}  // namespace off
+}  // namespace tvx
+
+using tvx::off::Shape;
+using tvx::off::Workspace;
+
+namespace {
+
+thread_local const char* g_off_err = "no error";
+
+int off_fail(int code, const char* msg) {
+  g_off_err = msg;
+  return code;
+}
+
+int check_shape(const tvolap_offline_shape* sh, Shape* S) {
+  if (!sh) return off_fail(TVOLAP_EINVAL, "shape is NULL");
+  if (!(sh->hop == 64 || sh->hop == 128 || sh->hop == 256 || sh->hop == 512))
+    return off_fail(TVOLAP_EINVAL, "hop must be 64, 128, 256 or 512");
+  if (sh->n_channels < 1 || sh->n_partitions < 1 || sh->n_slots < 1 || sh->n_samples < 1)
+    return off_fail(TVOLAP_EINVAL, "n_channels, n_partitions, n_slots and n_samples must be >= 1");
+  if (sh->n_channels > 65535) return off_fail(TVOLAP_EINVAL, "n_channels must be <= 65535");
+  const int64_t nblk = (sh->n_samples + sh->hop - 1) / sh->hop + 1;
+  if (nblk > (1 << 30)) return off_fail(TVOLAP_EINVAL, "n_samples too large");
+  S->L = sh->hop;
+  S->C = sh->n_channels;
+  S->K = sh->n_slots;
+  S->M = sh->n_partitions;
+  S->N = sh->n_samples;
+  S->nblk = (int32_t)nblk;
+  return TVOLAP_OK;
+}
+
+int prepare(const Shape& S, void* ws, int64_t ws_bytes, Workspace* w) {
+  if (!ws) return off_fail(TVOLAP_EINVAL, "workspace is NULL");
+  if (ws_bytes < tvx::off::workspace_layout(S, nullptr, nullptr)) return off_fail(TVOLAP_EINVAL, "workspace too small");
+  tvx::off::workspace_layout(S, w, static_cast<char*>(ws));
+  return TVOLAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tvolap_offline_last_error(void) { return g_off_err; }
+
+int64_t tvolap_offline_workspace_bytes(const tvolap_offline_shape* shape) {
+  Shape S;
+  if (check_shape(shape, &S) != TVOLAP_OK) return -1;
+  return tvx::off::workspace_layout(S, nullptr, nullptr);
+}
+
+int tvolap_offline_ir_spectra(const tvolap_offline_shape* shape, const float* taps, int32_t n_taps, float* H,
+                              void* stream) {
+  Shape S;
+  if (int rc = check_shape(shape, &S)) return rc;
+  if (!taps || !H) return off_fail(TVOLAP_EINVAL, "taps or H is NULL");
+  if (n_taps < 1 || n_taps > 2 * S.L * S.M) return off_fail(TVOLAP_EINVAL, "n_taps outside [1, 2L M]");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipError_t e = tvx::off::by_hop(S.L, [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    hipLaunchKernelGGL((tvx::off::k_ir_spectra<L>), dim3((unsigned)((int64_t)S.C * S.K * S.M)), dim3(tvx::off::T),
+                       0, st, S, taps, n_taps, reinterpret_cast<float2*>(H));
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return off_fail(TVOLAP_EDEVICE, hipGetErrorString(e));
+  return TVOLAP_OK;
+}
+
+int tvolap_offline_forward(const tvolap_offline_shape* shape, const float* x, const float* H,
+                           const int32_t* schedule, float* y, void* workspace, int64_t workspace_bytes,
+                           void* stream) {
+  Shape S;
+  if (int rc = check_shape(shape, &S)) return rc;
+  if (!x || !H || !y) return off_fail(TVOLAP_EINVAL, "x, H or y is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w;
+  if (int rc = prepare(S, workspace, workspace_bytes, &w)) return rc;
+  const dim3 gb(S.nblk, S.C);
+  const unsigned rows = (unsigned)((int64_t)S.C * S.K * S.M);
+  const unsigned ola_x = (unsigned)std::min<int64_t>((S.N + tvx::off::T - 1) / tvx::off::T, 65535);
+  const hipError_t e = tvx::off::by_hop(S.L, [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    using namespace tvx::off;
+    hipLaunchKernelGGL(k_pack, dim3(rows), dim3(T), 0, st, S, reinterpret_cast<const float2*>(H), w.Hp);
+    hipLaunchKernelGGL((k_spectra<L>), gb, dim3(T), 0, st, S, x, w.Xall);
+    hipLaunchKernelGGL((k_fwd_blocks<L>), gb, dim3(T), 0, st, S, w.Hp, w.Xall, schedule, w.blk);
+    hipLaunchKernelGGL(k_ola, dim3(ola_x, S.C), dim3(T), 0, st, S, w.blk, y);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return off_fail(TVOLAP_EDEVICE, hipGetErrorString(e));
+  return TVOLAP_OK;
+}
+
+int tvolap_offline_backward(const tvolap_offline_shape* shape, const float* x, const float* H,
+                            const int32_t* schedule, const float* gy, float* dx, float* dH, void* workspace,
+                            int64_t workspace_bytes, void* stream) {
+  Shape S;
+  if (int rc = check_shape(shape, &S)) return rc;
+  if (!x || !H || !gy) return off_fail(TVOLAP_EINVAL, "x, H or gy is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace w;
+  if (int rc = prepare(S, workspace, workspace_bytes, &w)) return rc;
+  const dim3 gb(S.nblk, S.C);
+  const unsigned rows = (unsigned)((int64_t)S.C * S.K * S.M);
+  const unsigned ola_x = (unsigned)std::min<int64_t>((S.N + tvx::off::T - 1) / tvx::off::T, 65535);
+  // the block buffer (4L floats per block) holds the 2L packed gradient spectra
+  float2* gspec = reinterpret_cast<float2*>(w.blk);
+  const hipError_t e = tvx::off::by_hop(S.L, [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    using namespace tvx::off;
+    hipLaunchKernelGGL(k_pack, dim3(rows), dim3(T), 0, st, S, reinterpret_cast<const float2*>(H), w.Hp);
+    hipLaunchKernelGGL((k_gspec<L>), gb, dim3(T), 0, st, S, gy, gspec);
+    if (dH) {
+      // delay line recomputed from x
+      hipLaunchKernelGGL((k_spectra<L>), gb, dim3(T), 0, st, S, x, w.Xall);
+      hipLaunchKernelGGL(k_dH, dim3(rows), dim3(T), 0, st, S, gspec, w.Xall, schedule,
+                         reinterpret_cast<float2*>(dH));
+    }
+    if (dx) {
+      // the input spectra are no longer needed: their space holds the windowed blocks
+      float* dxb = reinterpret_cast<float*>(w.Xall);
+      hipLaunchKernelGGL((k_dx_blocks<L>), gb, dim3(T), 0, st, S, gspec, w.Hp, schedule, dxb);
+      hipLaunchKernelGGL(k_dx_ola, dim3(ola_x, S.C), dim3(T), 0, st, S, dxb, dx);
+    }
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return off_fail(TVOLAP_EDEVICE, hipGetErrorString(e));
+  return TVOLAP_OK;
+}
+
+}  // extern "C"
