@@ -37,6 +37,8 @@ WORKLOADS = {
                         "each channel toggles with p=0.1 per block, 2 s at 48 kHz", fn="uneven", dtype="f32"),
     "plain": dict(desc="1 channel, L=128, 4096-tap IRs, 2 slots switched every 50 blocks, 10 s at 48 kHz",
                   fn="plain", dtype="f32"),
+    "autograd": dict(desc="32 channels, L=256, 8192-tap IRs (16 partitions), 2 s at 48 kHz, MSE loss against "
+                          "a target made by hidden IRs, gradients for H and x", fn="autograd", dtype="f32"),
 }
 
 
@@ -86,7 +88,18 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--graph", action="store_true",
                     help="capture one step (all blocks) in a HIP graph and replay it per step")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB float32 buffer 5 times (hardware-counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(args.calibrate_copy * (1 << 18), device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": a.numel() * 4, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); channels are independent, "
               "so more GPUs would shard channels with no communication", file=sys.stderr)
@@ -106,7 +119,61 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
+        if args.workload == "autograd":
+            return run_autograd(args, spec, wl)
         return run(args, spec, wl, stream)
+
+
+def run_autograd(args, spec, wl):
+    """Offline differentiable form: MSE loss against the hidden-IR target,
+    forward and backward (gradients for H and x) timed separately."""
+    import torch
+
+    from paper_2310_00319_amd import functional as F
+
+    C, N, L = wl.n_channels, wl.n_samples, wl.hop
+    taps = torch.from_numpy(np.stack([wl.taps[c][0] for c in range(C)])[:, None, :].copy()).cuda()
+    H = F.ir_spectra(taps, L).requires_grad_(True)
+    x = torch.from_numpy(wl.x).cuda().requires_grad_(True)
+    target = torch.from_numpy(wl.target).cuda()
+
+    def fwd():
+        return torch.mean((F.tvolap(x, H, L) - target) ** 2)
+
+    for _ in range(args.warmup):
+        fwd().backward()
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    f_ms = b_ms = 0.0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        x.grad = None
+        H.grad = None
+        e[0].record()
+        loss = fwd()
+        e[1].record()
+        loss.backward()
+        e[2].record()
+        torch.cuda.synchronize()
+        f_ms += e[0].elapsed_time(e[1])
+        b_ms += e[1].elapsed_time(e[2])
+    elapsed = time.perf_counter() - t0
+    f_ms /= args.steps
+    b_ms /= args.steps
+    ms_per_step = 1e3 * elapsed / args.steps
+    res = {
+        "metric": "channel-samples/s of one forward + backward pass (offline differentiable TVOLAP)",
+        "value": round(C * N / (ms_per_step / 1e3), 1),
+        "unit": "channel-samples/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"autograd: {spec['desc']}", "channels": C, "hop": L, "ir_taps": int(wl.max_taps()),
+                   "partitions": int(H.shape[2]), "samples": N},
+        "forward_ms": round(f_ms, 4), "backward_ms": round(b_ms, 4),
+        "backward_forward_ratio": round(b_ms / f_ms, 3),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
 
 
 def run(args, spec, wl, stream):

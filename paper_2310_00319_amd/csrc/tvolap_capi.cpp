@@ -36,8 +36,9 @@ struct TimingSet {
 // fused: 0 = three launches per block (transform-in, MAC, transform-out);
 // 1 = one launch (the last work item of a channel transforms back);
 // 2 = two launches (transform-in fused into the MAC, then transform-out).
+// vec: complex bins per lane for 16-bit storage (2 or 4; f32 always uses 2).
 struct MacChoice {
-  int32_t chunk = 0, waves = 4, grid = 0, fused = 1;
+  int32_t chunk = 0, waves = 4, grid = 0, fused = 1, vec = 4;
 };
 
 // Autotuner results, keyed by the handle's shape (hop, channels, inputs,
@@ -201,9 +202,9 @@ bool supported_hop(int L) { return L == 64 || L == 128 || L == 256 || L == 512; 
 // into chunks of `S` partitions. The partial-spectrum rows of a channel are
 // contiguous in (tile, chunk) order, so the channel's spectrum is the sum over
 // chunks of rows base + tile * nchunks + chunk.
-void build_work(tvolap_t* h, int S_req, int waves) {
+void build_work(tvolap_t* h, int S_req, int waves, int vec) {
   const int N = 2 * h->L;
-  const int V = (h->dtype == 0) ? 2 : std::min(4, N / 64);
+  const int V = (h->dtype == 0) ? 2 : std::min(vec == 2 ? 2 : 4, N / 64);
   h->shape.V = V;
   h->shape.NW = (waves == 8) ? 8 : 4;
   h->tile_width = 64 * V;
@@ -310,11 +311,12 @@ int upload_work(tvolap_t* h) {
 
 int apply_choice(tvolap_t* h, const MacChoice& c) {
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  build_work(h, c.chunk, c.waves);
+  build_work(h, c.chunk, c.waves, c.vec);
   RC_TRY(upload_work(h));
   h->choice = c;
   h->choice.chunk = h->chunk;
   h->choice.waves = h->shape.NW;
+  h->choice.vec = h->shape.V;
   return TVOLAP_OK;
 }
 
@@ -718,12 +720,15 @@ int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us) {
   MacChoice best;
   float best_t = 1e30f;
   int rc = TVOLAP_OK;
+  const std::vector<int> vecs = h->dtype == 0 ? std::vector<int>{2} : std::vector<int>{2, 4};
+  for (int vec : vecs)
   for (int mode : {1, 2})
   for (int S : chunks) {
     for (int nw : {4, 8}) {
       for (int gmul : {0, 1, 2, 4}) {
         MacChoice c;
         c.fused = mode;
+        c.vec = vec;
         c.chunk = S;
         c.waves = nw;
         c.grid = gmul * h->n_cu;

@@ -269,14 +269,17 @@ __device__ __forceinline__ void write_partials(const WorkItem& it, float2 (&acc)
 #pragma unroll
     for (int v = 0; v < V; ++v) red[w][g][lane * V + v] = acc[g][v];
   __syncthreads();
-  for (int e = tid; e < G * TW; e += 64 * NW) {
-    const int g = e / TW;
-    const int b = e - g * TW;
-    if (g < it.n_ch) {
-      float2 s = red[0][g][b];
+  // g runs over compile-time indices so that the item stays in registers
 #pragma unroll
-      for (int ww = 1; ww < NW; ++ww) s = cadd(s, red[ww][g][b]);
-      store_maybe<COHERENT>(ypart + (int64_t)it.row[g] * TW + b, s);
+  for (int g = 0; g < G; ++g) {
+    if (g < it.n_ch) {
+      float2* dst = ypart + (int64_t)it.row[g] * TW;
+      for (int b = tid; b < TW; b += 64 * NW) {
+        float2 s = red[0][g][b];
+#pragma unroll
+        for (int ww = 1; ww < NW; ++ww) s = cadd(s, red[ww][g][b]);
+        store_maybe<COHERENT>(dst + b, s);
+      }
     }
   }
 }
@@ -454,7 +457,9 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
         write_partials<V, G, NW, true>(it, acc, red, A.ypart, lane, w, tid);
         wait_memory();
         __syncthreads();
-        for (int g = 0; g < it.n_ch; ++g) arrive(it.ch[g]);
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (g < it.n_ch) arrive(it.ch[g]);
       } else {
         write_partials<V, G, NW, false>(it, acc, red, A.ypart, lane, w, tid);
         __syncthreads();
