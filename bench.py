@@ -1,13 +1,18 @@
-"""Benchmark: streaming TVOLAP throughput on one MI355X.
+"""Benchmark: TVOLAP throughput on one MI355X.
 
 A step is one pass of the whole hot path over the workload's signal: every
 block of the 5 s (binaural) input runs through window + transform-in, the
 spectral MAC against the partition spectra of the slot selected for that block,
-transform-out and overlap-add, for all channels. Inputs, IR bank, schedule and
-outputs are resident in HBM before timing starts.
+transform-out and overlap-add, for all channels, with the IR slot of every
+channel switching every block. Inputs, IR bank, schedule and outputs are
+resident in HBM before timing starts.
 
-Prints one JSON line (see the keys below) with the roofline of the spectral-MAC
-kernel (HIP events around every MAC launch over the timed region) and a CPU
+By default blocks go through the library 16 at a time (tvolap_process_blocks,
+output identical to one call per block); the same run also times strict
+streaming with one call per block (realtime_one_block_per_call).
+
+Prints one JSON line with the roofline of the dominant kernel (HIP events
+recorded by the library around its launches over the timed region) and a CPU
 baseline (the FP64 oracle on a bounded sample of the same workload).
 """
 from __future__ import annotations
@@ -86,6 +91,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=16,
+                    help="blocks per call (1 = strict streaming, one block per call; >1 = batched calls)")
+    ap.add_argument("--no-realtime", action="store_true",
+                    help="skip the extra one-block-per-call measurement")
     ap.add_argument("--graph", action="store_true",
                     help="capture one step (all blocks) in a HIP graph and replay it per step")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -183,7 +192,7 @@ def run(args, spec, wl, stream):
 
     conv = Convolver(hop=wl.hop, n_channels=wl.n_channels, max_taps=wl.max_taps(), n_inputs=wl.n_inputs,
                      input_of_channel=wl.input_of_channel, taps_of_channel=wl.taps_of_channel,
-                     n_slots=wl.n_slots, dtype=spec["dtype"], stream=stream)
+                     n_slots=wl.n_slots, dtype=spec["dtype"], stream=stream, max_batch=max(16, args.batch))
     t0 = time.perf_counter()
     for c in range(wl.n_channels):
         for s in range(wl.n_slots):
@@ -207,8 +216,11 @@ def run(args, spec, wl, stream):
     torch.cuda.synchronize()
 
     if args.graph:
+        if args.batch > 1:
+            conv.process(x[:, : wl.hop * args.batch], sched, out[:, : wl.hop * args.batch], batch=args.batch)
+            conv.reset()   # batch buffers are allocated outside the capture
         conv.capture_begin()
-        conv.process(x, sched, out)
+        conv.process(x, sched, out, batch=args.batch)
         conv.capture_end()
         log("captured one step as a HIP graph")
 
@@ -216,14 +228,14 @@ def run(args, spec, wl, stream):
         if args.graph:
             conv.graph_launch()
         else:
-            conv.process(x, sched, out)
+            conv.process(x, sched, out, batch=args.batch)
 
     for w in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log(f"warmup {w + 1}/{args.warmup} done")
 
-    per_kernel = not args.no_kernel_timing and not args.graph and args.mode != "fused"
+    per_kernel = not args.no_kernel_timing and not args.graph and (args.mode != "fused" or args.batch > 1)
     if per_kernel:
         conv.set_timing(True)
         conv.get_timing()
@@ -241,6 +253,7 @@ def run(args, spec, wl, stream):
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
     timing = conv.get_timing() if per_kernel else None
     conv.set_timing(False)
+    calls_per_step = -(-wl.n_calls // args.batch)
     if not per_kernel and not args.no_kernel_timing:
         # One kernel per block: the events that bracket the timed region on the
         # convolver's stream give its average launch duration (inter-launch
@@ -250,6 +263,21 @@ def run(args, spec, wl, stream):
         if info["fused"] != 1:
             timing = None
 
+    realtime = None
+    if args.batch > 1 and not args.no_realtime and not args.graph:
+        # strict streaming: one block per call, same workload
+        conv.process(x, sched, out, batch=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(max(1, args.steps // 2)):
+            conv.process(x, sched, out, batch=1)
+        torch.cuda.synchronize()
+        rt_ms = 1e3 * (time.perf_counter() - t1) / max(1, args.steps // 2)
+        realtime = {"value": round(wl.n_channels * wl.n_calls * wl.hop / (rt_ms / 1e3), 1),
+                    "unit": "channel-samples/s", "ms_per_step": round(rt_ms, 4),
+                    "us_per_block": round(1e3 * rt_ms / wl.n_calls, 3),
+                    "real_time_factor": round((wl.hop / wl.fs) / (1e-3 * rt_ms / wl.n_calls), 1)}
+
     ms_per_step = 1e3 * elapsed / args.steps
     blocks = wl.n_calls
     ch_samples = wl.n_channels * blocks * wl.hop
@@ -258,7 +286,20 @@ def run(args, spec, wl, stream):
     rtf = (wl.hop / wl.fs) / (us_per_block * 1e-6)
 
     roof = None
-    if timing and timing["blocks"] > 0:
+    if timing and timing["blocks"] > 0 and args.batch > 1:
+        # dominant kernel: k_batch_mac, one launch per call over its blocks
+        launches = args.steps * calls_per_step
+        mac_ms = timing["ms_mac"] / launches
+        kbytes = info["mac_bytes_per_block"] * wl.n_calls / calls_per_step
+        achieved = kbytes / (mac_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_batch_mac (spectral MAC of eq. 8 over a batch of blocks)",
+                "bytes_per_launch": int(kbytes), "avg_launch_us": round(mac_ms * 1e3, 3),
+                "phase_us_per_block": {"in": round(1e3 * timing["ms_in"] / timing["blocks"], 3),
+                                       "mac": round(1e3 * timing["ms_mac"] / timing["blocks"], 3),
+                                       "out": round(1e3 * timing["ms_out"] / timing["blocks"], 3)}}
+    elif timing and timing["blocks"] > 0:
         mac_ms = timing["ms_mac"] / timing["blocks"]
         if info["fused"] == 1:
             kbytes = info["block_bytes"]
@@ -307,6 +348,8 @@ def run(args, spec, wl, stream):
         "cpu_baseline": cpu,
         "ir_bank_load_s": round(t_setir, 3),
         "graph": bool(args.graph),
+        "blocks_per_call": args.batch,
+        "realtime_one_block_per_call": realtime,
         "schedule": {"mode": {1: "fused", 2: "two", 0: "plain"}[info["fused"]], "chunk": info["mac_chunk"],
                      "waves": info["mac_waves"], "grid": info["mac_grid"], "work_items": info["n_work_items"],
                      "autotuned_us_per_block": tuned_us},

@@ -64,6 +64,9 @@ typedef struct {
   int32_t spectra_dtype;            /* tvolap_dtype.                                     */
   void* stream;                     /* hipStream_t for all device work; NULL = the null
                                        stream.                                           */
+  int32_t max_batch;                /* largest n_blocks of tvolap_process_blocks, 0..1024
+                                       (0 = 16). The delay line keeps (max_batch-1)/2
+                                       extra spectra per parity.                         */
 } tvolap_config;
 
 /* Sizes of a handle, for accounting. Bytes count what one processed block must
@@ -89,8 +92,9 @@ typedef struct {
 
 /* Create a convolver (Sec. 2: partitioned, block-synchronously switchable,
  * multichannel). Allocates on the current HIP device: the IR bank
- * [C][K][M_c][2L], the delay line [I][2][M_i][2L] (M_i = max M_c over the
- * channels fed by input i), input history, overlap-add state, and tables
+ * [C][K][M_c][2L], the delay line [I][2][M_i + (max_batch-1)/2][2L] (M_i =
+ * max M_c over the channels fed by input i), input history, overlap-add
+ * state, and tables
  * (twiddles and window computed in double precision on the host). The bank is
  * zeroed (all slots hold a zero IR), the stream state is reset and every
  * channel selects slot 0. Synchronous. *out receives the handle, or NULL on an
@@ -134,6 +138,22 @@ int tvolap_select_ir(tvolap_t* h, const int32_t* slot_of_channel);
  * Errors: EINVAL (NULL in/out, stride < L). */
 int tvolap_process_block(tvolap_t* h, const float* in, int64_t in_stride, float* out,
                          int64_t out_stride, const int32_t* slot_of_channel_dev);
+
+/* Process n_blocks consecutive blocks at once (1 <= n_blocks <= max_batch):
+ * exactly the same results as n_blocks calls of tvolap_process_block, block j
+ * reading in[i*in_stride + j*L + n] and writing out[c*out_stride + j*L + n]
+ * (n < L), with the slots of block j at slots_dev[j*slots_stride + c] (device
+ * array, values clamped into [0, K)) or, if slots_dev is NULL, the current
+ * selection for all of them. The last block's slots become the selection.
+ * Three launches: the input spectra of all blocks, the spectral MAC of all
+ * blocks (inverse transforms done by the last work item of each block and
+ * channel), the overlap-add in call order. A larger n amortises the fixed
+ * cost of a block. The first call with a new MAC schedule allocates the
+ * batch buffers (waits for the stream). Errors: EINVAL (NULL in/out, n_blocks
+ * out of range, strides too small), ESTATE (allocation needed during graph
+ * capture), ENOMEM, EDEVICE. */
+int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32_t n_blocks, float* out,
+                          int64_t out_stride, const int32_t* slots_dev, int64_t slots_stride);
 
 /* Zero the delay line, the input history and the overlap-add state and
  * restart the call count (the bank and the selection are kept). Stream
@@ -179,12 +199,13 @@ int tvolap_capture_begin(tvolap_t* h);
 int tvolap_capture_end(tvolap_t* h);
 int tvolap_graph_launch(tvolap_t* h);
 
-/* Kernel timing. With enable != 0, every processed block records HIP events
- * on the handle's stream around its kernels. tvolap_get_timing waits for the
- * recorded blocks and returns the summed milliseconds of the transform-in,
- * spectral-MAC and transform-out phases and the number of blocks they cover,
- * then clears the sums. Phases that run fused inside one kernel report their
- * time under the MAC. */
+/* Kernel timing. With enable != 0, every process_block / process_blocks call
+ * records HIP events on the handle's stream around its kernels.
+ * tvolap_get_timing waits for the recorded calls and returns the summed
+ * milliseconds of the transform-in, spectral-MAC and transform-out phases and
+ * the number of blocks they cover, then clears the sums. Phases that run fused
+ * inside one kernel report their time under the MAC (for a batched call the
+ * MAC phase is the one kernel that runs the MAC of all its blocks). */
 int tvolap_set_timing(tvolap_t* h, int32_t enable);
 int tvolap_get_timing(tvolap_t* h, double* ms_in, double* ms_mac, double* ms_out,
                       int64_t* n_blocks);

@@ -27,7 +27,7 @@ DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 
 EXPORTED = (
     "tvolap_create", "tvolap_destroy", "tvolap_set_ir", "tvolap_select_ir",
-    "tvolap_process_block", "tvolap_reset", "tvolap_get_info", "tvolap_get_partitions",
+    "tvolap_process_block", "tvolap_process_blocks", "tvolap_reset", "tvolap_get_info", "tvolap_get_partitions",
     "tvolap_set_timing", "tvolap_get_timing", "tvolap_last_error", "tvolap_version",
     "tvolap_configure", "tvolap_autotune", "tvolap_capture_begin", "tvolap_capture_end",
     "tvolap_graph_launch", "tvolap_offline_workspace_bytes", "tvolap_offline_ir_spectra",
@@ -56,6 +56,7 @@ class TvolapConfig(ctypes.Structure):
         ("n_slots", ctypes.c_int32),
         ("spectra_dtype", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("max_batch", ctypes.c_int32),
     ]
 
 
@@ -112,6 +113,7 @@ def _declare(lib):
     lib.tvolap_set_ir.argtypes = [c_vp, c_i32, c_i32, c_vp, c_i32, c_i32]
     lib.tvolap_select_ir.argtypes = [c_vp, c_vp]
     lib.tvolap_process_block.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp]
+    lib.tvolap_process_blocks.argtypes = [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_vp, c_i64]
     lib.tvolap_reset.argtypes = [c_vp]
     lib.tvolap_get_info.argtypes = [c_vp, ctypes.POINTER(TvolapInfo)]
     lib.tvolap_get_partitions.argtypes = [c_vp, c_vp]

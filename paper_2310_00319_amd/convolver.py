@@ -31,11 +31,12 @@ class Convolver:
     taps_of_channel   [C] IR length of each channel (default max_taps).
     n_slots           K IR slots per channel.
     dtype             storage of IR spectra and delay line: "f32", "bf16", "f16".
+    max_batch         largest number of blocks per batched call (process(..., batch=n)).
     """
 
     def __init__(self, hop: int, n_channels: int, max_taps: int, n_inputs: int | None = None,
                  input_of_channel=None, taps_of_channel=None, n_slots: int = 1, dtype: str = "f32",
-                 device=None, stream: torch.cuda.Stream | None = None):
+                 device=None, stream: torch.cuda.Stream | None = None, max_batch: int = 16):
         self._lib = load()
         self._h = ctypes.c_void_p()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
@@ -45,6 +46,7 @@ class Convolver:
         self.n_inputs = int(n_inputs if n_inputs is not None else n_channels)
         self.n_slots = int(n_slots)
         self.dtype = dtype
+        self.max_batch = int(max_batch)
         if dtype not in DTYPES:
             raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
         with torch.cuda.device(self.device):
@@ -66,6 +68,7 @@ class Convolver:
             cfg.n_slots = self.n_slots
             cfg.spectra_dtype = DTYPES[dtype]
             cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
+            cfg.max_batch = self.max_batch
             check(self._lib.tvolap_create(ctypes.byref(cfg), ctypes.byref(self._h)), None)
             self._keep = []
 
@@ -131,10 +134,11 @@ class Convolver:
         return out
 
     def process(self, x: torch.Tensor, schedule: torch.Tensor | None = None,
-                out: torch.Tensor | None = None) -> torch.Tensor:
-        """Stream a resident signal: x [I][n*L] -> out [C][n*L], one
-        process_block per L samples; schedule [n][C] int32 (device) gives the
-        slots of every call."""
+                out: torch.Tensor | None = None, batch: int = 1) -> torch.Tensor:
+        """Stream a resident signal: x [I][n*L] -> out [C][n*L]; schedule
+        [n][C] int32 (device) gives the slots of every block. batch = 1: one
+        process_block per L samples; batch > 1: process_blocks over up to
+        `batch` blocks at a time (same results)."""
         L = self.hop
         self._check_2d(x, self.n_inputs, "x")
         n = x.shape[1] // L
@@ -147,12 +151,23 @@ class Convolver:
             if not schedule.is_cuda or schedule.dtype != torch.int32 or not schedule.is_contiguous() \
                     or schedule.dim() != 2 or schedule.shape[0] < n or schedule.shape[1] != self.n_channels:
                 raise ValueError("schedule must be a contiguous CUDA int32 tensor [n_calls][n_channels]")
-        fn = self._lib.tvolap_process_block
         h = self._h
         xp, xs = x.data_ptr(), int(x.stride(0))
         op, os_ = out.data_ptr(), int(out.stride(0))
         sp = schedule.data_ptr() if schedule is not None else None
         row = self.n_channels * 4
+        if batch > 1:
+            if batch > self.max_batch:
+                raise ValueError(f"batch {batch} exceeds max_batch {self.max_batch}")
+            fnb = self._lib.tvolap_process_blocks
+            for c in range(0, n, batch):
+                k = min(batch, n - c)
+                rc = fnb(h, xp + 4 * L * c, xs, k, op + 4 * L * c, os_,
+                         (sp + row * c) if sp is not None else None, self.n_channels)
+                if rc != 0:
+                    check(rc, h)
+            return out
+        fn = self._lib.tvolap_process_block
         for c in range(n):
             rc = fn(h, xp + 4 * L * c, xs, op + 4 * L * c, os_, (sp + row * c) if sp is not None else None)
             if rc != 0:

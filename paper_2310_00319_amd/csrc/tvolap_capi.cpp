@@ -15,6 +15,7 @@
 #include "../../include/tvolap.h"
 #include "tvolap_internal.h"
 
+using tvx::BatchArgs;
 using tvx::BlockArgs;
 using tvx::DevPlan;
 using tvx::MacShape;
@@ -30,7 +31,8 @@ constexpr int kSelRing = 16;
 struct TimingSet {
   hipEvent_t ev[4];
   bool pending = false;
-  int mode = 0;   // launch mode of the recorded block (see MacChoice::fused)
+  int mode = 0;     // launch mode of the recorded call (see MacChoice::fused)
+  int blocks = 1;   // blocks covered by the recorded call
 };
 
 // fused: 0 = three launches per block (transform-in, MAC, transform-out);
@@ -54,7 +56,10 @@ struct tvolap {
   int device = 0;
   int n_cu = 256;
   hipStream_t stream = nullptr;
-  std::vector<int32_t> ch_input, ch_taps, ch_M, in_M;
+  std::vector<int32_t> ch_input, ch_taps, ch_M;
+  std::vector<int32_t> in_M;      // delay-line ring length per parity: M_i + ring_extra
+  std::vector<int32_t> in_Mdata;  // M_i = max M_c over the channels of input i
+  int32_t max_batch = 16, ring_extra = 7;
   std::vector<int64_t> ch_bank_off, in_fdl_off;
   int64_t bank_elems = 0, fdl_elems = 0;
   size_t store_bytes = 8;  // bytes per stored complex value
@@ -89,13 +94,20 @@ struct tvolap {
   int32_t chunk = 0;
   std::vector<WorkItem> items;    // n_spec spectrum items, then n_mac MAC items
   int32_t n_spec = 0, n_mac = 0;
-  std::vector<int32_t> ch_row_base, ch_nchunks, needed;
+  std::vector<int32_t> ch_row_base, ch_nchunks, needed, needed_mac;
   int32_t n_rows = 0;
   WorkItem* d_items = nullptr;
   float2* d_ypart = nullptr;    // [n_rows][tile_width]
   int32_t* d_ch_row_base = nullptr;
   int32_t* d_ch_nchunks = nullptr;
   int32_t* d_needed = nullptr;
+  int32_t* d_needed_mac = nullptr;
+
+  // batched blocks
+  float2* d_bypart = nullptr;     // [max_batch][n_rows][tile_width]
+  int32_t* d_barrive = nullptr;   // [max_batch][C]
+  float* d_yblk = nullptr;        // [max_batch][C][4L]
+  int64_t bypart_elems = 0;
 
   // pinned staging ring for host slot selections
   int32_t* h_sel_ring = nullptr;  // [kSelRing][C], hipHostMalloc
@@ -114,7 +126,7 @@ struct tvolap {
   TimingSet tsets[kTimingRing];
   int tnext = 0;
   double ms_in = 0, ms_mac = 0, ms_out = 0;
-  int64_t t_blocks = 0;
+  int64_t t_blocks = 0, t_calls = 0;
   bool events_made = false;
 
   std::string err = "no error";
@@ -173,6 +185,9 @@ void free_work(tvolap_t* h) {
   dfree(h->d_ch_row_base);
   dfree(h->d_ch_nchunks);
   dfree(h->d_needed);
+  dfree(h->d_needed_mac);
+  dfree(h->d_bypart);
+  h->bypart_elems = 0;
 }
 
 void free_all(tvolap_t* h) {
@@ -185,7 +200,7 @@ void free_all(tvolap_t* h) {
   dfree(h->d_counter); dfree(h->d_tw); dfree(h->d_win); dfree(h->d_ch_input); dfree(h->d_ch_M);
   dfree(h->d_ch_bank_off); dfree(h->d_in_M); dfree(h->d_in_fdl_off); dfree(h->d_taps);
   dfree(h->d_arrive); dfree(h->d_done); dfree(h->d_zero_in); dfree(h->d_tune_out); dfree(h->d_tune_sel);
-  dfree(h->d_in_ch_ptr); dfree(h->d_in_ch);
+  dfree(h->d_in_ch_ptr); dfree(h->d_in_ch); dfree(h->d_barrive); dfree(h->d_yblk);
   if (h->events_made)
     for (auto& t : h->tsets)
       for (auto& e : t.ev) (void)hipEventDestroy(e);
@@ -248,8 +263,11 @@ void build_work(tvolap_t* h, int S_req, int waves, int vec) {
   h->ch_nchunks.assign(h->C, 0);
   h->needed.assign(h->C, 0);
   int row = 0;
+  // every channel has at least one MAC item (possibly over no partitions), so
+  // that in batched mode each (block, channel) pair has an item that completes it
+  auto chunks_of = [&](const Sub& s) { return std::max(1, (s.M - 1 + S - 1) / S); };
   for (auto& s : subs) {
-    const int nch = (s.M - 1 + S - 1) / S;
+    const int nch = chunks_of(s);
     for (int c : s.ch) {
       h->ch_row_base[c] = row;
       h->ch_nchunks[c] = nch;
@@ -262,14 +280,14 @@ void build_work(tvolap_t* h, int S_req, int waves, int vec) {
   struct Tmp { WorkItem w; int size; };
   std::vector<Tmp> tmp;
   for (auto& s : subs) {
-    const int nch = (s.M - 1 + S - 1) / S;
+    const int nch = chunks_of(s);
     for (int t = 0; t < T; ++t)
       for (int j = 0; j < nch; ++j) {
         WorkItem w{};
         w.kind = 0;
         w.input = s.input;
         w.n_ch = (int)s.ch.size();
-        w.m0 = 1 + j * S;
+        w.m0 = std::min(s.M, 1 + j * S);
         w.m1 = std::min(s.M, 1 + (j + 1) * S);
         w.tile = t;
         w.chunk = j;
@@ -293,6 +311,8 @@ void build_work(tvolap_t* h, int S_req, int waves, int vec) {
   for (auto& t : tmp) h->items.push_back(t.w);
   h->n_spec = h->I;
   h->n_mac = (int32_t)tmp.size();
+  h->needed_mac.resize(h->C);
+  for (int c = 0; c < h->C; ++c) h->needed_mac[c] = h->needed[c] - 1;
 }
 
 int upload_work(tvolap_t* h) {
@@ -302,10 +322,12 @@ int upload_work(tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_ch_row_base, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_ch_nchunks, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_needed, (size_t)h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_needed_mac, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, hipMemcpy(h->d_items, h->items.data(), h->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_ch_row_base, h->ch_row_base.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_ch_nchunks, h->ch_nchunks.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_needed, h->needed.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_needed_mac, h->needed_mac.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
   return TVOLAP_OK;
 }
 
@@ -351,8 +373,13 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
     h->ch_taps[c] = cfg->taps_of_channel ? cfg->taps_of_channel[c] : cfg->max_taps;
     h->ch_M[c] = (h->ch_taps[c] + N - 1) / N;
   }
-  h->in_M.assign(h->I, 1);
-  for (int c = 0; c < h->C; ++c) h->in_M[h->ch_input[c]] = std::max(h->in_M[h->ch_input[c]], h->ch_M[c]);
+  h->max_batch = cfg->max_batch > 0 ? cfg->max_batch : 16;
+  h->ring_extra = (h->max_batch - 1) / 2;
+  h->in_Mdata.assign(h->I, 1);
+  for (int c = 0; c < h->C; ++c)
+    h->in_Mdata[h->ch_input[c]] = std::max(h->in_Mdata[h->ch_input[c]], h->ch_M[c]);
+  h->in_M.resize(h->I);
+  for (int i = 0; i < h->I; ++i) h->in_M[i] = h->in_Mdata[i] + h->ring_extra;
   h->ch_bank_off.resize(h->C);
   int64_t off = 0;
   for (int c = 0; c < h->C; ++c) {
@@ -387,6 +414,9 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_zero_in, (size_t)h->I * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_tune_out, (size_t)h->C * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_tune_sel, (size_t)h->K * h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_barrive, (size_t)h->max_batch * h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_yblk, (size_t)h->max_batch * h->C * 4 * L * sizeof(float)));
+  HIP_TRY(h, hipMemsetAsync(h->d_barrive, 0, (size_t)h->max_batch * h->C * sizeof(int32_t), h->stream));
   HIP_TRY(h, dalloc(&h->d_in_ch_ptr, (size_t)(h->I + 1) * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_in_ch, (size_t)h->C * sizeof(int32_t)));
   {
@@ -458,7 +488,8 @@ void drain_timing(tvolap_t* h, TimingSet& t) {
     h->ms_in += a;
     h->ms_mac += b;
     h->ms_out += c;
-    h->t_blocks += 1;
+    h->t_blocks += t.blocks;
+    h->t_calls += 1;
   }
   t.pending = false;
 }
@@ -476,6 +507,7 @@ int enqueue_block(tvolap_t* h, const float* in, int64_t in_stride, float* out, i
     h->tnext = (h->tnext + 1) % kTimingRing;
     drain_timing(h, *ts);
     ts->mode = h->choice.fused;
+    ts->blocks = 1;
   }
   if (h->choice.fused) {
     BlockArgs A;
@@ -534,6 +566,7 @@ int reset_state(tvolap_t* h) {
   HIP_TRY(h, tvx::launch_fill_zero(h->d_counter, sizeof(uint64_t), h->stream));
   HIP_TRY(h, tvx::launch_fill_zero(h->d_arrive, (size_t)h->C * sizeof(int32_t), h->stream));
   HIP_TRY(h, tvx::launch_fill_zero(h->d_done, sizeof(int32_t), h->stream));
+  HIP_TRY(h, tvx::launch_fill_zero(h->d_barrive, (size_t)h->max_batch * h->C * sizeof(int32_t), h->stream));
   return TVOLAP_OK;
 }
 
@@ -565,6 +598,8 @@ int tvolap_create(const tvolap_config* cfg, tvolap_t** out) {
     return fail(nullptr, TVOLAP_EINVAL, "n_channels, n_inputs, n_slots and max_taps must be >= 1");
   if (cfg->spectra_dtype < 0 || cfg->spectra_dtype > 2)
     return fail(nullptr, TVOLAP_EINVAL, "spectra_dtype must be TVOLAP_F32, TVOLAP_BF16 or TVOLAP_F16");
+  if (cfg->max_batch < 0 || cfg->max_batch > 1024)
+    return fail(nullptr, TVOLAP_EINVAL, "max_batch must be in [0, 1024]");
   if (!cfg->input_of_channel && cfg->n_inputs != cfg->n_channels)
     return fail(nullptr, TVOLAP_EINVAL, "input_of_channel is NULL but n_inputs != n_channels");
   for (int c = 0; c < cfg->n_channels; ++c) {
@@ -661,6 +696,58 @@ int tvolap_process_block(tvolap_t* h, const float* in, int64_t in_stride, float*
   if (!in || !out) return fail(h, TVOLAP_EINVAL, "in or out is NULL");
   if (in_stride < h->L || out_stride < h->L) return fail(h, TVOLAP_EINVAL, "stride smaller than hop");
   return enqueue_block(h, in, in_stride, out, out_stride, slot_of_channel_dev, slot_of_channel_dev != nullptr);
+}
+
+int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32_t n_blocks, float* out,
+                          int64_t out_stride, const int32_t* slots_dev, int64_t slots_stride) {
+  if (!h) return TVOLAP_EINVAL;
+  if (!in || !out) return fail(h, TVOLAP_EINVAL, "in or out is NULL");
+  if (n_blocks < 1 || n_blocks > h->max_batch) return fail(h, TVOLAP_EINVAL, "n_blocks outside [1, max_batch]");
+  if (in_stride < (int64_t)n_blocks * h->L && h->I > 1)
+    return fail(h, TVOLAP_EINVAL, "in_stride smaller than n_blocks * hop");
+  if (out_stride < (int64_t)n_blocks * h->L && h->C > 1)
+    return fail(h, TVOLAP_EINVAL, "out_stride smaller than n_blocks * hop");
+  if (slots_dev && slots_stride < h->C) return fail(h, TVOLAP_EINVAL, "slots_stride smaller than n_channels");
+  const int64_t need = (int64_t)h->max_batch * h->n_rows * h->tile_width;
+  if (h->bypart_elems < need) {
+    if (h->capturing) return fail(h, TVOLAP_ESTATE, "batch buffers must be allocated before graph capture");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    dfree(h->d_bypart);
+    HIP_TRY(h, dalloc(&h->d_bypart, (size_t)need * sizeof(float2)));
+    h->bypart_elems = need;
+  }
+  BatchArgs B;
+  B.P = h->plan();
+  B.items = h->d_items + h->n_spec;
+  B.n_mac = h->n_mac;
+  B.n_blocks = n_blocks;
+  B.n_rows = h->n_rows;
+  B.bank = h->d_bank;
+  B.fdl = h->d_fdl;
+  B.sel = slots_dev ? slots_dev : h->d_sel;
+  B.sel_stride = slots_dev ? slots_stride : 0;
+  B.sel_store = h->d_sel;
+  B.copy_sel = slots_dev ? 1 : 0;
+  B.ypart = h->d_bypart;
+  B.arrive = h->d_barrive;
+  B.needed = h->d_needed_mac;
+  B.yblk = h->d_yblk;
+  B.ola_state = h->d_ola;
+  B.done = h->d_done;
+  B.counter = h->d_counter;
+  const int grid = n_blocks * h->n_mac;
+  TimingSet* ts = nullptr;
+  if (h->timing && !h->capturing) {
+    ts = &h->tsets[h->tnext];
+    h->tnext = (h->tnext + 1) % kTimingRing;
+    drain_timing(h, *ts);
+    ts->mode = 0;          // three phases: spectra, MAC, overlap-add
+    ts->blocks = n_blocks;
+  }
+  HIP_TRY(h, tvx::launch_batch(B, h->dtype, h->shape, grid, in, in_stride, h->d_hist, h->d_ola, out, out_stride,
+                               h->stream, ts ? ts->ev : nullptr));
+  if (ts) ts->pending = true;
+  return TVOLAP_OK;
 }
 
 int tvolap_reset(tvolap_t* h) {
@@ -825,7 +912,7 @@ int tvolap_get_info(const tvolap_t* h, tvolap_info* info) {
   info->bins = N;
   int64_t sm = 0, si = 0;
   for (int c = 0; c < h->C; ++c) sm += h->ch_M[c];
-  for (int i = 0; i < h->I; ++i) si += h->in_M[i];
+  for (int i = 0; i < h->I; ++i) si += h->in_Mdata[i];
   info->sum_partitions = sm;
   info->sum_input_partitions = si;
   // The MAC reads the M_c active partition spectra of every channel and, per
@@ -875,6 +962,7 @@ int tvolap_get_timing(tvolap_t* h, double* ms_in, double* ms_mac, double* ms_out
   if (n_blocks) *n_blocks = h->t_blocks;
   h->ms_in = h->ms_mac = h->ms_out = 0;
   h->t_blocks = 0;
+  h->t_calls = 0;
   return TVOLAP_OK;
 }
 

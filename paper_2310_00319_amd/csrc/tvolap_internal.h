@@ -79,6 +79,33 @@ hipError_t launch_inv(const DevPlan& P, int dtype, const float2* ypart, const vo
                       const int32_t* sel, float* ola, float* out, int64_t out_stride, int32_t copy_sel,
                       int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s);
 hipError_t launch_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s);
+
+// Batches of consecutive blocks (see k_batch_* in tvolap_kernels.hip).
+struct BatchArgs {
+  DevPlan P;
+  const WorkItem* items;       // MAC items of one block
+  int32_t n_mac;
+  int32_t n_blocks;
+  int32_t n_rows;              // partial rows of one block
+  const void* bank;
+  void* fdl;
+  const int32_t* sel;          // [n_blocks][sel_stride] slots (caller's or the handle's with stride 0)
+  int64_t sel_stride;
+  int32_t* sel_store;
+  int32_t copy_sel;
+  float2* ypart;               // [n_max][rows][tile_width]
+  int32_t* arrive;             // [n_max][C]
+  const int32_t* needed;       // [C] MAC items per channel
+  float* yblk;                 // [n_max][C][4L]
+  float* ola_state;            // [C][3L]
+  int32_t* done;
+  uint64_t* counter;
+};
+// ev (may be NULL): four events recorded before the spectra, before the MAC,
+// before the overlap-add and after it.
+hipError_t launch_batch(const BatchArgs& B, int dtype, const MacShape& shape, int grid, const float* in,
+                        int64_t in_stride, float* hist, float* ola, float* out, int64_t out_stride, hipStream_t s,
+                        hipEvent_t* ev);
 hipError_t launch_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M,
                          void* dst, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -325,18 +325,16 @@ __device__ __forceinline__ void inverse_ola(float2* Y, float2* bufA, float2* buf
   }
 }
 
-// Complete channel c: Y = sum of its partial tiles (partitions m >= 1) +
-// H_{c, slot}(0) X(l) (eq. 8, m = 0 term, X(l) read back from the delay
-// line), then transform back and overlap-add. COHERENT: the partial tiles and
-// X(l) were published by other workgroups of the same launch.
+// Spectrum of channel c for this block into Y (LDS): the sum of its partial
+// tiles (partitions m >= 1) plus H_{c, slot}(0) X(l) (eq. 8, m = 0 term, X(l)
+// read back from the delay line). COHERENT: the partial tiles and X(l) were
+// published by other workgroups of the same launch. No barrier at the end.
 template <int L, int T, int DT, bool COHERENT>
-__device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __restrict__ ypart,
-                                              const typename Store<DT>::T* __restrict__ bank,
-                                              const typename Store<DT>::T* __restrict__ fdl,
-                                              const int32_t* __restrict__ sel, int c, int p, uint64_t cnt,
-                                              float2* Y, float2* bufA, float2* bufB, const float2* twl,
-                                              float* __restrict__ ola, float* __restrict__ out, int64_t out_stride,
-                                              int tid) {
+__device__ __forceinline__ void channel_spectrum(const DevPlan& P, const float2* __restrict__ ypart,
+                                                 const typename Store<DT>::T* __restrict__ bank,
+                                                 const typename Store<DT>::T* __restrict__ fdl,
+                                                 const int32_t* __restrict__ sel, int c, int p, uint64_t cnt,
+                                                 float2* Y, int tid) {
   using ST = typename Store<DT>::T;
   constexpr int N = 2 * L;
   const int TW = P.tile_width;
@@ -348,9 +346,6 @@ __device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __
   int s = sel[c];
   s = s < 0 ? 0 : (s >= P.K ? P.K - 1 : s);
   const ST* h0 = bank + P.ch_bank_off[c] + (int64_t)s * P.ch_M[c] * N;
-  float* st = ola + (int64_t)c * 3 * L;
-  float old[(4 * L + T - 1) / T];
-  ola_prefetch<L, T>(st, old, tid);    // in flight together with the loads below
 #pragma unroll
   for (int k = tid; k < N; k += T) {
     const float2 X = unpack<DT>(load_maybe<COHERENT>(xrow + k));
@@ -371,8 +366,41 @@ __device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __
     for (; j < nch; ++j) s0 = cadd(s0, load_maybe<COHERENT>(src + (int64_t)j * TW));
     Y[k] = cadd(cadd(s0, s1), cadd(s2, s3));
   }
+}
+
+// Complete channel c: spectrum, inverse transform and overlap-add.
+template <int L, int T, int DT, bool COHERENT>
+__device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __restrict__ ypart,
+                                              const typename Store<DT>::T* __restrict__ bank,
+                                              const typename Store<DT>::T* __restrict__ fdl,
+                                              const int32_t* __restrict__ sel, int c, int p, uint64_t cnt,
+                                              float2* Y, float2* bufA, float2* bufB, const float2* twl,
+                                              float* __restrict__ ola, float* __restrict__ out, int64_t out_stride,
+                                              int tid) {
+  float* st = ola + (int64_t)c * 3 * L;
+  float old[(4 * L + T - 1) / T];
+  ola_prefetch<L, T>(st, old, tid);    // in flight together with the spectrum's loads
+  channel_spectrum<L, T, DT, COHERENT>(P, ypart, bank, fdl, sel, c, p, cnt, Y, tid);
   __syncthreads();
   inverse_ola<L, T>(Y, bufA, bufB, twl, old, st, out + (int64_t)c * out_stride, tid);
+}
+
+// Inverse real DFT of the packed spectrum Y (eq. 9): the 4L samples of the
+// block's output go to dst.
+template <int L, int T>
+__device__ __forceinline__ void inverse_store(float2* Y, float2* bufA, float2* bufB, const float2* twl,
+                                              float* __restrict__ dst, int tid) {
+  constexpr int N = 2 * L;
+#pragma unroll
+  for (int k = tid; k < N; k += T) bufA[k] = fft::real_inv_pre_conj<N>(Y, k, twl);
+  __syncthreads();
+  const float2* R = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  constexpr float scale = 1.0f / (float)(4 * L);
+#pragma unroll
+  for (int n = tid; n < 4 * L; n += T) {
+    const float2 z = R[n >> 1];
+    dst[n] = ((n & 1) ? -z.y : z.x) * scale;
+  }
 }
 
 // ---------------------------------------------------------------- fused per-block kernel
@@ -474,6 +502,161 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
       }
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- batched blocks
+
+// Batches of n consecutive blocks (calls cnt .. cnt+n-1) in three launches:
+// all input spectra, one MAC launch whose last item per (block, channel)
+// transforms back into a block buffer, and a per-channel overlap-add in call
+// order. The delay line holds M_i + (n_max-1)/2 spectra per parity, so a
+// batch's new spectra never replace ones that its own blocks still read.
+
+// Spectrum of input i for block j of the batch (block j's 2L samples are the
+// previous call's L samples, from the history for j = 0, then its own L).
+template <int L, int DT>
+__global__ __launch_bounds__(256) void k_batch_spectra(DevPlan P, const float* __restrict__ in, int64_t in_stride,
+                                                       const float* __restrict__ hist,
+                                                       typename Store<DT>::T* __restrict__ fdl,
+                                                       const uint64_t* __restrict__ counter) {
+  constexpr int N = 2 * L;
+  constexpr int T = 256;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  const int j = blockIdx.x, i = blockIdx.y, tid = threadIdx.x;
+  const uint64_t cnt = *counter + (uint64_t)j;
+  const int p = (int)(cnt & 1u);
+  load_tables<L, T>(P, twl, winl, tid);
+  const float* xin = in + (int64_t)i * in_stride + (int64_t)j * L;
+  const float* hold = (j == 0) ? hist + ((size_t)(p ^ 1) * P.I + i) * L : xin - L;
+  for (int n = tid; n < L; n += T) {
+    const int t0 = 2 * n, t1 = 2 * n + 1;
+    const float s0 = (t0 < L) ? hold[t0] : xin[t0 - L];
+    const float s1 = (t1 < L) ? hold[t1] : xin[t1 - L];
+    bufA[n] = make_float2(P.win[t0] * s0, P.win[t1] * s1);
+    bufA[n + L] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const float2* Z = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  const int Mi = P.in_M[i];
+  typename Store<DT>::T* dst = fdl + P.in_fdl_off[i] + ((int64_t)p * Mi + ring_slot(cnt, Mi)) * N;
+  for (int k = tid; k < N; k += T) dst[k] = pack<DT>(fft::real_fwd_post<N>(Z, k, twl));
+}
+
+// MAC items of all blocks of the batch (block-major order). The last item to
+// finish a (block, channel) pair writes that block's 4L output samples.
+template <int L, int V, int G, int NW, int DT>
+__global__ __launch_bounds__(64 * NW) void k_batch_mac(BatchArgs B) {
+  using ST = typename Store<DT>::T;
+  constexpr int N = 2 * L;
+  constexpr int T = 64 * NW;
+  constexpr int TW = 64 * V;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  __shared__ float2 ybuf[N];
+  __shared__ float2 red[NW][G][TW];
+  __shared__ int flag;
+  const DevPlan& P = B.P;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const uint64_t cnt0 = *B.counter;
+  const ST* bank = static_cast<const ST*>(B.bank);
+  const ST* fdl = static_cast<const ST*>(B.fdl);
+  load_tables<L, T>(P, twl, winl, tid);
+  const int total = B.n_blocks * B.n_mac;
+  for (int idx = blockIdx.x; idx < total; idx += gridDim.x) {
+    const int j = idx / B.n_mac;
+    const WorkItem it = B.items[idx - j * B.n_mac];
+    const uint64_t cnt = cnt0 + (uint64_t)j;
+    const int p = (int)(cnt & 1u);
+    const int32_t* sel = B.sel + (int64_t)j * B.sel_stride;
+    float2* ypart = B.ypart + (int64_t)j * B.n_rows * TW;
+    int32_t* arrive = B.arrive + (int64_t)j * P.C;
+    float2 acc[G][V];
+    mac_item<V, G, NW, DT, 2>(P, it, bank, fdl, sel, p, cnt, lane, w, acc);
+    write_partials<V, G, NW, true>(it, acc, red, ypart, lane, w, tid);
+    wait_memory();
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (g < it.n_ch) {
+        const int c = it.ch[g];
+        if (tid == 0) flag = (atomicAdd(&arrive[c], 1) == B.needed[c] - 1) ? 1 : 0;
+        __syncthreads();
+        if (flag) {
+          channel_spectrum<L, T, DT, true>(P, ypart, bank, fdl, sel, c, p, cnt, ybuf, tid);
+          __syncthreads();
+          inverse_store<L, T>(ybuf, bufA, bufB, twl, B.yblk + ((int64_t)j * P.C + c) * 4 * L, tid);
+          if (tid == 0) arrive[c] = 0;
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// One workgroup per channel (and per input for the history): overlap-add the
+// batch's blocks in call order, carry the state, store the last history, and
+// advance the call count by n once every workgroup has read it.
+template <int L>
+__global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __restrict__ in, int64_t in_stride,
+                                                   float* __restrict__ hist, float* __restrict__ ola,
+                                                   float* __restrict__ out, int64_t out_stride) {
+  constexpr int T = 256;
+  constexpr int NPT = (4 * L + T - 1) / T;
+  const DevPlan& P = B.P;
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const uint64_t cnt0 = *B.counter;
+  if (c < P.C) {
+    float* st = ola + (int64_t)c * 3 * L;
+    float acc[NPT];   // acc[j] holds state(n), n = tid + j T (n < 3L), for the next block
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int n = tid + q * T;
+      acc[q] = (n < 3 * L) ? st[n] : 0.f;
+    }
+    __shared__ float sh[4 * L];
+    for (int j = 0; j < B.n_blocks; ++j) {
+      const float* y = B.yblk + ((int64_t)j * P.C + c) * 4 * L;
+      float* o = out + (int64_t)c * out_stride + (int64_t)j * L;
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const int n = tid + q * T;
+        if (n < 4 * L) sh[n] = acc[q] + y[n];   // state(n) + y(n); state(n) = 0 for n >= 3L
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NPT; ++q) {
+        const int n = tid + q * T;
+        if (n < L) o[n] = sh[n];
+        acc[q] = (n < 3 * L) ? sh[n + L] : 0.f;   // shift by L
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int n = tid + q * T;
+      if (n < 3 * L) st[n] = acc[q];
+    }
+    if (tid == 0 && B.copy_sel) B.sel_store[c] = B.sel[(int64_t)(B.n_blocks - 1) * B.sel_stride + c];
+  }
+  if (c < P.I) {
+    const uint64_t last = cnt0 + (uint64_t)(B.n_blocks - 1);
+    float* hnew = hist + ((size_t)(last & 1u) * P.I + c) * L;
+    const float* xin = in + (int64_t)c * in_stride + (int64_t)(B.n_blocks - 1) * L;
+    for (int n = tid; n < L; n += T) hnew[n] = xin[n];
+  }
+  if (tid == 0) {
+    if (atomicAdd(B.done, 1) == (int)gridDim.x - 1) {
+      *B.done = 0;
+      *B.counter = cnt0 + (uint64_t)B.n_blocks;
+    }
   }
 }
 
@@ -681,6 +864,45 @@ hipError_t launch_block(const BlockArgs& A, int dtype, const MacShape& shape, in
           return hipGetLastError();
         }
       });
+    });
+  });
+}
+
+hipError_t launch_batch(const BatchArgs& B, int dtype, const MacShape& shape, int grid, const float* in,
+                        int64_t in_stride, float* hist, float* ola, float* out, int64_t out_stride, hipStream_t s,
+                        hipEvent_t* ev) {
+  if (B.n_blocks <= 0) return hipSuccess;
+  return by_hop(B.P.L, [&](auto Lc) {
+    return by_dtype(dtype, [&](auto Dc) {
+      constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value;
+      using ST = typename Store<DT>::T;
+      hipError_t e = hipSuccess;
+      if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_batch_spectra<L, DT>), dim3(B.n_blocks, B.P.I), dim3(256), 0, s, B.P, in, in_stride,
+                         hist, static_cast<ST*>(B.fdl), B.counter);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+      if (B.n_mac > 0) {
+        e = by_shape(shape, [&](auto Vc, auto Gc, auto NWc) {
+          constexpr int V = decltype(Vc)::value, G = decltype(Gc)::value, NW = decltype(NWc)::value;
+          if constexpr (64 * V > 2 * L) {
+            return hipErrorInvalidValue;
+          } else {
+            hipLaunchKernelGGL((k_batch_mac<L, V, G, NW, DT>), dim3(grid), dim3(64 * NW), 0, s, B);
+            return hipGetLastError();
+          }
+        });
+        if (e != hipSuccess) return e;
+      }
+      if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+      const int wgs = B.P.C > B.P.I ? B.P.C : B.P.I;
+      hipLaunchKernelGGL((k_batch_ola<L>), dim3(wgs), dim3(256), 0, s, B, in, in_stride, hist, B.ola_state, out,
+                         out_stride);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      if (ev) e = hipEventRecord(ev[3], s);
+      return e;
     });
   });
 }

@@ -65,7 +65,7 @@ def make_convolver(wl, dtype: str = "f32", stream=None, mode: str = "fused"):
     return conv
 
 
-def gpu_streams(wl, dtype: str = "f32", conv=None, mode: str = "fused"):
+def gpu_streams(wl, dtype: str = "f32", conv=None, mode: str = "fused", batch: int = 1):
     """Whole workload through the library with a device-resident schedule.
     Returns the [C][n_calls*L] output as float64 numpy."""
     import torch
@@ -75,7 +75,7 @@ def gpu_streams(wl, dtype: str = "f32", conv=None, mode: str = "fused"):
         conv = make_convolver(wl, dtype, mode=mode)
     x = torch.from_numpy(wl.padded_input()).cuda()
     sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
-    out = conv.process(x, sched)
+    out = conv.process(x, sched, batch=batch)
     torch.cuda.synchronize()
     res = out.cpu().numpy().astype(np.float64)
     if own:

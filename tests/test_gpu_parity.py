@@ -253,3 +253,59 @@ def test_full_uneven_workload_sampled_channels():
     lens = wl.taps_of_channel
     chans = sorted({int(np.argmax(lens)), int(np.argmin(lens)), 0, 255, 511})
     _check(wl, channels=chans, name="uneven-full")
+
+
+# ------------------------------------------------------------------ batched blocks
+
+@pytest.mark.parametrize("case", SMALL_CASES[:5], ids=[f"s{c[0]}_L{c[1]}" for c in SMALL_CASES[:5]])
+@pytest.mark.parametrize("batch", [2, 5, 16])
+def test_batched_blocks_equal_single_blocks(case, batch):
+    """process_blocks(n) gives bit-identical output to n process_block calls
+    (same MAC schedule, same summation order), and matches the oracle."""
+    seed, L, C, I, N, tr, K, p = case
+    log(f"batched case {case} batch {batch}")
+    wl = synth.random_small(seed=seed, hop=L, n_channels=C, n_inputs=I, n_samples=N,
+                            taps_range=tr, n_slots=K, p_switch=p)
+    single = gpu_streams(wl)
+    batched = gpu_streams(wl, batch=batch)
+    assert np.array_equal(single, batched)
+    ref = oracle_streams(wl)
+    assert rel_rms_per_channel(batched, ref).max() <= TOL_F32
+
+
+def test_batched_mixed_with_single_calls_and_host_selection():
+    """Alternating single and batched calls, host selections and NULL device
+    schedules keep one continuous stream."""
+    import torch
+    log("mixed batched/single")
+    wl = synth.random_small(seed=51, hop=128, n_channels=6, n_inputs=3, n_samples=128 * 40,
+                            taps_range=(500, 4000), n_slots=3, p_switch=0.4)
+    ref = gpu_streams(wl).astype(np.float32)
+    conv = make_convolver(wl)
+    L, C = wl.hop, wl.n_channels
+    x = torch.from_numpy(wl.padded_input()).cuda()
+    sched = torch.from_numpy(wl.schedule.astype(np.int32)).cuda()
+    out = torch.zeros((C, wl.n_calls * L), device="cuda")
+    lib, h = conv._lib, conv._h
+    c = 0
+    pattern = [1, 3, 1, 7, 2, 16, 1, 5]
+    k = 0
+    while c < wl.n_calls:
+        n = min(pattern[k % len(pattern)], wl.n_calls - c)
+        k += 1
+        if n == 1 and k % 3 == 0:
+            conv.select_ir(wl.schedule[c])
+            conv.process_block(x[:, c * L:(c + 1) * L], out[:, c * L:(c + 1) * L])
+        elif k % 4 == 0 and np.all(wl.schedule[c:c + n] == wl.schedule[c]):
+            conv.select_ir(wl.schedule[c])
+            assert lib.tvolap_process_blocks(h, x.data_ptr() + 4 * L * c, x.stride(0), n,
+                                             out.data_ptr() + 4 * L * c, out.stride(0), None, 0) == 0
+        else:
+            assert lib.tvolap_process_blocks(h, x.data_ptr() + 4 * L * c, x.stride(0), n,
+                                             out.data_ptr() + 4 * L * c, out.stride(0),
+                                             sched.data_ptr() + 4 * C * c, C) == 0
+        c += n
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    conv.close()
+    assert np.array_equal(got, ref)
