@@ -38,6 +38,8 @@ WORKLOADS = {
                      fn="binaural", dtype="f32"),
     "binaural_bf16": dict(desc="as binaural, IR spectra and delay line stored bf16", fn="binaural", dtype="bf16"),
     "binaural_f16": dict(desc="as binaural, IR spectra and delay line stored f16", fn="binaural", dtype="f16"),
+    "binaural_r2": dict(desc="as binaural with hop 128 (blocks 256, FFT 512): the 2-s IRs fall into 375 partitions",
+                        fn="binaural", kw=dict(hop=128), dtype="f32"),
     "uneven": dict(desc="512 channels, L=128, IR lengths log-uniform 4800..192000 taps, 2 slots, "
                         "each channel toggles with p=0.1 per block, 2 s at 48 kHz", fn="uneven", dtype="f32"),
     "plain": dict(desc="1 channel, L=128, 4096-tap IRs, 2 slots switched every 50 blocks, 10 s at 48 kHz",
@@ -51,8 +53,42 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, budget_s: float) -> dict:
-    """FP64 oracle on the first channels of the workload until the budget is spent."""
+KERNEL_SOURCES = ("tvolap_kernels.hip", "fft_lds.hpp", "tvolap_internal.h")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2310_00319_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(case: str):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary of this case
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when no summary covers
+    the case or the kernel sources changed since the counters were taken."""
+    import glob
+    want = kernel_sources_sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith((" ", "|", "#")):
+                    k, v = line.split(":", 1)
+                    kv[k.split(" (")[0].strip()] = v.strip()
+        if kv.get("traffic_case") == case and kv.get("kernel_sources_sha256") == want:
+            try:
+                return int(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+            except (KeyError, ValueError):
+                return None
+    return None
+
+
+def cpu_baseline(wl, budget_s: float, keep: list | None = None) -> dict:
+    """FP64 oracle on the first channels of the workload until the budget is
+    spent. The outputs of the channels it finished are appended to ``keep``."""
     import oracle as orc
 
     x = wl.padded_input().astype(np.float64)
@@ -61,7 +97,9 @@ def cpu_baseline(wl, budget_s: float) -> dict:
     done = 0
     for c in range(wl.n_channels):
         H = orc.channel_spectra([t.astype(np.float64) for t in wl.taps[c]], wl.hop, int(wl.taps_of_channel[c]))
-        orc.tvolap_stream(x[wl.input_of_channel[c]], H, wl.schedule[:, c], wl.hop, wl.n_calls)
+        y = orc.tvolap_stream(x[wl.input_of_channel[c]], H, wl.schedule[:, c], wl.hop, wl.n_calls)
+        if keep is not None:
+            keep.append(y)
         done += 1
         if time.perf_counter() - t_wall > budget_s:
             break
@@ -122,7 +160,7 @@ def main():
     spec = WORKLOADS[args.workload]
     log(f"workload {args.workload}: {spec['desc']}")
     t0 = time.perf_counter()
-    wl = getattr(synth, spec["fn"])()
+    wl = getattr(synth, spec["fn"])(**spec.get("kw", {}))
     log(f"generated in {time.perf_counter() - t0:.1f} s: C={wl.n_channels} I={wl.n_inputs} L={wl.hop} "
         f"calls={wl.n_calls}")
     torch.cuda.set_device(0)
@@ -292,8 +330,11 @@ def run(args, spec, wl, stream):
         mac_ms = timing["ms_mac"] / launches
         kbytes = info["mac_bytes_per_block"] * wl.n_calls / calls_per_step
         achieved = kbytes / (mac_ms * 1e-3) / 1e9
+        tr = measured_traffic(f"{args.workload} batch{args.batch} k_batch_mac")
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr[0] if tr else None,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_source": tr[1] if tr else None,
                 "kernel": "k_batch_mac (spectral MAC of eq. 8 over a batch of blocks)",
                 "bytes_per_launch": int(kbytes), "avg_launch_us": round(mac_ms * 1e3, 3),
                 "phase_us_per_block": {"in": round(1e3 * timing["ms_in"] / timing["blocks"], 3),
@@ -321,9 +362,25 @@ def run(args, spec, wl, stream):
                                        "out": round(1e3 * timing["ms_out"] / timing["blocks"], 3)}}
 
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(wl, args.cpu_budget)
+        ref = []
+        cpu = cpu_baseline(wl, args.cpu_budget, ref)
+        # accuracy of the same configuration: one fresh pass (untimed) from a
+        # reset state, compared per channel with the oracle channels above
+        conv.reset()
+        conv.process(x, sched, out, batch=args.batch)
+        torch.cuda.synchronize()
+        got = out[: len(ref)].double().cpu().numpy()
+        ref = np.stack(ref)
+        rel = np.sqrt(np.sum((got - ref) ** 2, axis=1) / np.maximum(np.sum(ref ** 2, axis=1), 1e-300))
+        snr = -20.0 * np.log10(np.maximum(rel, 1e-30))
+        accuracy = {"vs": "FP64 oracle (unquantized)", "channels": int(len(ref)),
+                    "max_rel_rms": float(f"{rel.max():.3e}"),
+                    "snr_db": {"min": round(float(snr.min()), 2), "median": round(float(np.median(snr)), 2),
+                               "max": round(float(snr.max()), 2)}}
+        log(f"accuracy: {accuracy}")
 
     res = {
         "metric": "channel-samples/s at L=256, 2-s IRs (FP32 vs BF16/batched); % HBM peak",
@@ -336,7 +393,7 @@ def run(args, spec, wl, stream):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": spec["dtype"],
+        "dtype": "f32",   # transforms and accumulation; spectra storage is config.spectra_dtype
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {spec['desc']}", "channels": wl.n_channels,
                    "inputs": wl.n_inputs, "hop": wl.hop, "ir_taps": int(wl.max_taps()),
@@ -346,6 +403,7 @@ def run(args, spec, wl, stream):
         "real_time_factor": round(rtf, 1),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "accuracy": accuracy,
         "ir_bank_load_s": round(t_setir, 3),
         "graph": bool(args.graph),
         "blocks_per_call": args.batch,
