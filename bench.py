@@ -107,8 +107,17 @@ def cpu_baseline(wl, budget_s: float, keep: list | None = None) -> dict:
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
     samples = done * wl.n_calls * wl.hop
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": samples / wall, "unit": "channel-samples/s", "cores": max(1, int(round(cpu / wall))),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": model,
             "sample": f"FP64 oracle, first {done} of {wl.n_channels} channels over the full "
                       f"{wl.n_calls}-block stream ({wall:.1f} s wall, {cpu:.1f} s CPU)"}
 

@@ -34,6 +34,12 @@ Readings where the paper is silent, ambiguous or self-inconsistent:
   R-bins   Only the 2L + 1 non-negative-frequency bins are kept; the inverse
            transform takes the Hermitian extension and ignores the imaginary
            parts at k = 0 and k = 2L.
+
+Pins: every function is checked by tests against results fixed independently
+of this module (brute-force convolution, a time-domain block definition, a
+closed-form cross-fade, hand-worked goldens, a naive DFT, finite differences),
+except ``quantized_tvolap_streams``: parity unpinned as a whole (its rounding
+step ``quantize`` is pinned; the rest is the pinned streaming oracle).
 """
 from __future__ import annotations
 
