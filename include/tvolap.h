@@ -88,6 +88,14 @@ typedef struct {
   int32_t mac_grid;                 /* MAC workgroups launched (each loops over items)   */
   int32_t fused;                    /* launches per block: 1 -> one, 2 -> two, 0 -> three */
   int32_t n_cu;                     /* compute units of the device                       */
+  /* batched calls (tvolap_process_blocks): time-blocked MAC schedule          */
+  int32_t batch_chunk;              /* partitions per work item                          */
+  int32_t batch_vec;                /* complex bins per lane                             */
+  int32_t batch_waves;              /* waves per workgroup (each owns 64 vec bins)       */
+  int32_t batch_tile_width;         /* bins per work item: 64 vec waves                  */
+  int32_t batch_work_items;         /* items per time group (parity class of up to 8
+                                       blocks of a batch)                                */
+  int32_t batch_rows;               /* partial-spectrum rows per block                   */
 } tvolap_info;
 
 /* Create a convolver (Sec. 2: partitioned, block-synchronously switchable,
@@ -140,18 +148,18 @@ int tvolap_process_block(tvolap_t* h, const float* in, int64_t in_stride, float*
                          int64_t out_stride, const int32_t* slot_of_channel_dev);
 
 /* Process n_blocks consecutive blocks at once (1 <= n_blocks <= max_batch):
- * exactly the same results as n_blocks calls of tvolap_process_block, block j
- * reading in[i*in_stride + j*L + n] and writing out[c*out_stride + j*L + n]
- * (n < L), with the slots of block j at slots_dev[j*slots_stride + c] (device
- * array, values clamped into [0, K)) or, if slots_dev is NULL, the current
- * selection for all of them. The last block's slots become the selection.
- * Three launches: the input spectra of all blocks, the spectral MAC of all
- * blocks (inverse transforms done by the last work item of each block and
- * channel), the overlap-add in call order. A larger n amortises the fixed
- * cost of a block. The first call with a new MAC schedule allocates the
- * batch buffers (waits for the stream). Errors: EINVAL (NULL in/out, n_blocks
- * out of range, strides too small), ESTATE (allocation needed during graph
- * capture), ENOMEM, EDEVICE. */
+ * the same results as n_blocks calls of tvolap_process_block (up to the order
+ * of floating-point additions in the spectral MAC), block j reading
+ * in[i*in_stride + j*L + n] and writing out[c*out_stride + j*L + n] (n < L),
+ * with the slots of block j at slots_dev[j*slots_stride + c] (device array,
+ * values clamped into [0, K)) or, if slots_dev is NULL, the current selection
+ * for all of them. The last block's slots become the selection. Four
+ * launches: the input spectra of all blocks (eq. 1-6), the spectral MAC of
+ * all blocks (eq. 8) in time groups of same-parity blocks that share
+ * delay-line and partition-spectrum reads, the inverse transforms (eq. 9) and
+ * the overlap-add in call order (eq. 10-13). No allocation; the call is
+ * asynchronous and may be captured in a graph. Errors: EINVAL (NULL in/out,
+ * n_blocks out of range, strides too small), EDEVICE. */
 int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32_t n_blocks, float* out,
                           int64_t out_stride, const int32_t* slots_dev, int64_t slots_stride);
 
@@ -188,6 +196,27 @@ int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, i
  * receives the best time per block in microseconds, or -1 when the choice came
  * from the cache. Synchronous. Errors: EINVAL, ESTATE during capture, EDEVICE. */
 int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us);
+
+/* Schedule of batched calls (tvolap_process_blocks; no effect on results
+ * beyond the order of floating-point additions). The spectral MAC of a batch
+ * works on time groups: up to 8 blocks of the same parity, which read
+ * overlapping delay-line spectra (block l + 2 at partition m + 1 reads what
+ * block l reads at partition m, eq. 8) and, where their slots agree, the same
+ * partition spectra. chunk: partitions per work item (0 = about one workgroup
+ * per compute unit); vec: complex bins per lane (1 or 2; 0 = 2); waves: 1, 2 or 4 waves per workgroup,
+ * each owning 64 vec bins (0 = 4, fewer when 2L bins are fewer). Waits for
+ * the stream; rebuilds the batched work list. Errors: EINVAL, ESTATE during
+ * capture, ENOMEM/EDEVICE. */
+int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves);
+
+/* Autotuner for batched calls: times `iters` calls of max_batch blocks (zero
+ * input, current bank, block b of the batch in slot b mod K) for each
+ * candidate (vec, waves, chunk), keeps the fastest, caches it for handles of
+ * the same shape and max_batch in this process, then resets the stream state
+ * as tvolap_reset does. *best_us (may be NULL) receives the best time per
+ * block in microseconds, or -1 when the choice came from the cache.
+ * Synchronous. Errors: EINVAL, ESTATE during capture, EDEVICE. */
+int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us);
 
 /* HIP graph capture of the handle's stream (which must not be the null
  * stream). Device work enqueued between begin and end (process_block with

@@ -29,7 +29,8 @@ EXPORTED = (
     "tvolap_create", "tvolap_destroy", "tvolap_set_ir", "tvolap_select_ir",
     "tvolap_process_block", "tvolap_process_blocks", "tvolap_reset", "tvolap_get_info", "tvolap_get_partitions",
     "tvolap_set_timing", "tvolap_get_timing", "tvolap_last_error", "tvolap_version",
-    "tvolap_configure", "tvolap_autotune", "tvolap_capture_begin", "tvolap_capture_end",
+    "tvolap_configure", "tvolap_autotune", "tvolap_configure_batch", "tvolap_autotune_batch",
+    "tvolap_capture_begin", "tvolap_capture_end",
     "tvolap_graph_launch", "tvolap_offline_workspace_bytes", "tvolap_offline_ir_spectra",
     "tvolap_offline_forward", "tvolap_offline_backward", "tvolap_offline_last_error",
 )
@@ -78,6 +79,12 @@ class TvolapInfo(ctypes.Structure):
         ("mac_grid", ctypes.c_int32),
         ("fused", ctypes.c_int32),
         ("n_cu", ctypes.c_int32),
+        ("batch_chunk", ctypes.c_int32),
+        ("batch_vec", ctypes.c_int32),
+        ("batch_waves", ctypes.c_int32),
+        ("batch_tile_width", ctypes.c_int32),
+        ("batch_work_items", ctypes.c_int32),
+        ("batch_rows", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -124,6 +131,8 @@ def _declare(lib):
     lib.tvolap_last_error.restype = ctypes.c_char_p
     lib.tvolap_configure.argtypes = [c_vp, c_i32, c_i32, c_i32, c_i32]
     lib.tvolap_autotune.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_float)]
+    lib.tvolap_configure_batch.argtypes = [c_vp, c_i32, c_i32, c_i32]
+    lib.tvolap_autotune_batch.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_float)]
     lib.tvolap_capture_begin.argtypes = [c_vp]
     lib.tvolap_capture_end.argtypes = [c_vp]
     lib.tvolap_graph_launch.argtypes = [c_vp]

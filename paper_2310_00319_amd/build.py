@@ -1,5 +1,9 @@
 """Build libtvolap.so for gfx950 in-tree with hipcc.
 
+The kernel file is compiled once per supported hop (64, 128, 256, 512); all
+translation units compile in parallel and are then linked into one shared
+library.
+
 Usage: python -m paper_2310_00319_amd.build   (or call build()).
 """
 from __future__ import annotations
@@ -8,18 +12,25 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtvolap.so")
-SOURCES = ["tvolap_kernels.hip", "tvolap_offline.hip", "tvolap_capi.cpp"]
+HOPS = (64, 128, 256, 512)
+# (source, extra flags, object name)
+UNITS = [("tvolap_kernels.hip", [f"-DTVX_HOP={L}"], f"tvolap_kernels_L{L}.o") for L in HOPS] + [
+    ("tvolap_offline.hip", [], "tvolap_offline.o"),
+    ("tvolap_dispatch.cpp", [], "tvolap_dispatch.o"),
+    ("tvolap_capi.cpp", [], "tvolap_capi.o"),
+]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # keep the compiler from emitting packed FP32 vector ALU instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -33,15 +44,29 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *srcs, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + proc.stdout + proc.stderr)
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + proc.stdout + proc.stderr)
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    cc = hipcc()
+    cmds = []
+    objs = []
+    for src, extra, obj in UNITS:
+        o = os.path.join(OBJ, obj)
+        objs.append(o)
+        cmds.append([cc, *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", o])
+    jobs = jobs or max(1, min(len(cmds), (os.cpu_count() or 2) - 1))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

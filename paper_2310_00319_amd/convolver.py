@@ -183,6 +183,15 @@ class Convolver:
         check(self._lib.tvolap_autotune(self._h, int(iters), ctypes.byref(best)), self._h)
         return best.value
 
+    def configure_batch(self, chunk: int = 0, vec: int = 0, waves: int = 0):
+        """Schedule of batched calls (process with batch > 1)."""
+        check(self._lib.tvolap_configure_batch(self._h, int(chunk), int(vec), int(waves)), self._h)
+
+    def autotune_batch(self, iters: int = 5) -> float:
+        best = ctypes.c_float()
+        check(self._lib.tvolap_autotune_batch(self._h, int(iters), ctypes.byref(best)), self._h)
+        return best.value
+
     def capture_begin(self):
         check(self._lib.tvolap_capture_begin(self._h), self._h)
 

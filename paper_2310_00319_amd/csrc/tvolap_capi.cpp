@@ -43,10 +43,18 @@ struct MacChoice {
   int32_t chunk = 0, waves = 4, grid = 0, fused = 1, vec = 4;
 };
 
+// Schedule of the time-blocked MAC of batched calls: partitions per item
+// (0 = automatic), complex bins per lane (0 = automatic), waves per tile
+// (0 = automatic).
+struct BatchChoice {
+  int32_t chunk = 0, vec = 0, waves = 0;
+};
+
 // Autotuner results, keyed by the handle's shape (hop, channels, inputs,
 // dtype, input map and partition counts).
 std::mutex g_tune_mu;
 std::map<std::string, MacChoice> g_tune_cache;
+std::map<std::string, BatchChoice> g_btune_cache;
 
 }  // namespace
 
@@ -94,20 +102,26 @@ struct tvolap {
   int32_t chunk = 0;
   std::vector<WorkItem> items;    // n_spec spectrum items, then n_mac MAC items
   int32_t n_spec = 0, n_mac = 0;
-  std::vector<int32_t> ch_row_base, ch_nchunks, needed, needed_mac;
+  std::vector<int32_t> ch_row_base, ch_nchunks, needed;
   int32_t n_rows = 0;
   WorkItem* d_items = nullptr;
   float2* d_ypart = nullptr;    // [n_rows][tile_width]
   int32_t* d_ch_row_base = nullptr;
   int32_t* d_ch_nchunks = nullptr;
   int32_t* d_needed = nullptr;
-  int32_t* d_needed_mac = nullptr;
 
-  // batched blocks
-  float2* d_bypart = nullptr;     // [max_batch][n_rows][tile_width]
-  int32_t* d_barrive = nullptr;   // [max_batch][C]
+  // batched blocks: time-blocked MAC work list (partitions from 0)
+  MacShape bshape{2, 1, 4};
+  BatchChoice bchoice;
+  int32_t b_tile_width = 512, b_chunk = 0, n_bmac = 0, n_brows = 0;
+  std::vector<WorkItem> bitems;
+  std::vector<int32_t> b_row_base, b_nchunks;
+  WorkItem* d_bitems = nullptr;
+  int32_t* d_brow_base = nullptr;
+  int32_t* d_bnchunks = nullptr;
+  float2* d_bypart = nullptr;     // [max_batch][n_brows][b_tile_width]
   float* d_yblk = nullptr;        // [max_batch][C][4L]
-  int64_t bypart_elems = 0;
+  int32_t* d_tune_bsel = nullptr; // [max_batch][C] autotuner schedule (slot = block mod K)
 
   // pinned staging ring for host slot selections
   int32_t* h_sel_ring = nullptr;  // [kSelRing][C], hipHostMalloc
@@ -185,9 +199,13 @@ void free_work(tvolap_t* h) {
   dfree(h->d_ch_row_base);
   dfree(h->d_ch_nchunks);
   dfree(h->d_needed);
-  dfree(h->d_needed_mac);
+}
+
+void free_batch_work(tvolap_t* h) {
+  dfree(h->d_bitems);
+  dfree(h->d_brow_base);
+  dfree(h->d_bnchunks);
   dfree(h->d_bypart);
-  h->bypart_elems = 0;
 }
 
 void free_all(tvolap_t* h) {
@@ -196,11 +214,12 @@ void free_all(tvolap_t* h) {
   h->graph_exec = nullptr;
   h->graph = nullptr;
   free_work(h);
+  free_batch_work(h);
   dfree(h->d_bank); dfree(h->d_fdl); dfree(h->d_hist); dfree(h->d_ola); dfree(h->d_sel);
   dfree(h->d_counter); dfree(h->d_tw); dfree(h->d_win); dfree(h->d_ch_input); dfree(h->d_ch_M);
   dfree(h->d_ch_bank_off); dfree(h->d_in_M); dfree(h->d_in_fdl_off); dfree(h->d_taps);
   dfree(h->d_arrive); dfree(h->d_done); dfree(h->d_zero_in); dfree(h->d_tune_out); dfree(h->d_tune_sel);
-  dfree(h->d_in_ch_ptr); dfree(h->d_in_ch); dfree(h->d_barrive); dfree(h->d_yblk);
+  dfree(h->d_in_ch_ptr); dfree(h->d_in_ch); dfree(h->d_yblk); dfree(h->d_tune_bsel);
   if (h->events_made)
     for (auto& t : h->tsets)
       for (auto& e : t.ev) (void)hipEventDestroy(e);
@@ -311,8 +330,94 @@ void build_work(tvolap_t* h, int S_req, int waves, int vec) {
   for (auto& t : tmp) h->items.push_back(t.w);
   h->n_spec = h->I;
   h->n_mac = (int32_t)tmp.size();
-  h->needed_mac.resize(h->C);
-  for (int c = 0; c < h->C; ++c) h->needed_mac[c] = h->needed[c] - 1;
+}
+
+// Work list of the time-blocked MAC (batched calls): channels grouped by
+// input (up to 2 per item), the 2L bins cut into tiles of 64 V NW, each
+// group's partitions [0, M) cut into chunks of S. The partial rows of a
+// channel are contiguous in (tile, chunk) order. Each item runs once per
+// time group (a parity class of up to kTimeBlock blocks of the batch).
+void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
+  const int N = 2 * h->L;
+  int V = (bc.vec == 1) ? 1 : 2;
+  while (64 * V > N && V > 1) V /= 2;
+  int NW = bc.waves > 0 ? bc.waves : 4;
+  NW = NW >= 4 ? 4 : (NW >= 2 ? 2 : 1);
+  while (64 * V * NW > N && NW > 1) NW /= 2;
+  h->bshape.V = V;
+  h->bshape.NW = NW;
+  h->b_tile_width = 64 * V * NW;
+  const int T = N / h->b_tile_width;
+
+  std::vector<std::vector<int>> by_input(h->I);
+  for (int c = 0; c < h->C; ++c) by_input[h->ch_input[c]].push_back(c);
+  int fan = 1;
+  for (auto& v : by_input) fan = std::max<int>(fan, (int)v.size());
+  const int G = fan >= 2 ? 2 : 1;
+  h->bshape.G = G;
+  struct Sub { int input; std::vector<int> ch; int M; };
+  std::vector<Sub> subs;
+  for (int i = 0; i < h->I; ++i) {
+    auto& v = by_input[i];
+    for (size_t j = 0; j < v.size(); j += G) {
+      Sub sb;
+      sb.input = i;
+      sb.M = 0;
+      for (size_t k = j; k < std::min(v.size(), j + (size_t)G); ++k) {
+        sb.ch.push_back(v[k]);
+        sb.M = std::max(sb.M, h->ch_M[v[k]]);
+      }
+      subs.push_back(sb);
+    }
+  }
+  int S = bc.chunk;
+  if (S <= 0) {
+    // about two workgroups per compute unit for a 16-block batch (two time groups)
+    int64_t units = 0;
+    for (auto& sb : subs) units += (int64_t)sb.M * T;
+    const int64_t target = h->n_cu;
+    S = (int)std::max<int64_t>(4, (units + target - 1) / target);
+  }
+  h->b_chunk = S;
+  h->b_row_base.assign(h->C, 0);
+  h->b_nchunks.assign(h->C, 0);
+  int row = 0;
+  auto chunks_of = [&](const Sub& sb) { return std::max(1, (sb.M + S - 1) / S); };
+  for (auto& sb : subs) {
+    const int nch = chunks_of(sb);
+    for (int c : sb.ch) {
+      h->b_row_base[c] = row;
+      h->b_nchunks[c] = nch;
+      row += nch * T;
+    }
+  }
+  h->n_brows = row;
+  struct Tmp { WorkItem w; int size; };
+  std::vector<Tmp> tmp;
+  for (auto& sb : subs) {
+    const int nch = chunks_of(sb);
+    for (int t = 0; t < T; ++t)
+      for (int j = 0; j < nch; ++j) {
+        WorkItem w{};
+        w.kind = 0;
+        w.input = sb.input;
+        w.n_ch = (int)sb.ch.size();
+        w.m0 = std::min(sb.M, j * S);
+        w.m1 = std::min(sb.M, (j + 1) * S);
+        w.tile = t;
+        w.chunk = j;
+        for (int g = 0; g < 4; ++g) {
+          const int c = g < w.n_ch ? sb.ch[g] : sb.ch[0];
+          w.ch[g] = c;
+          w.row[g] = h->b_row_base[c] + t * nch + j;
+        }
+        tmp.push_back({w, w.m1 - w.m0});
+      }
+  }
+  std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp& a, const Tmp& b) { return a.size > b.size; });
+  h->bitems.clear();
+  for (auto& t : tmp) h->bitems.push_back(t.w);
+  h->n_bmac = (int32_t)h->bitems.size();
 }
 
 int upload_work(tvolap_t* h) {
@@ -322,12 +427,32 @@ int upload_work(tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_ch_row_base, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_ch_nchunks, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_needed, (size_t)h->C * sizeof(int32_t)));
-  HIP_TRY(h, dalloc(&h->d_needed_mac, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, hipMemcpy(h->d_items, h->items.data(), h->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_ch_row_base, h->ch_row_base.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_ch_nchunks, h->ch_nchunks.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_needed, h->needed.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIP_TRY(h, hipMemcpy(h->d_needed_mac, h->needed_mac.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
+  return TVOLAP_OK;
+}
+
+int upload_batch_work(tvolap_t* h) {
+  free_batch_work(h);
+  HIP_TRY(h, dalloc(&h->d_bitems, h->bitems.size() * sizeof(WorkItem)));
+  HIP_TRY(h, dalloc(&h->d_brow_base, (size_t)h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_bnchunks, (size_t)h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_bypart, (size_t)h->max_batch * h->n_brows * h->b_tile_width * sizeof(float2)));
+  HIP_TRY(h, hipMemcpy(h->d_bitems, h->bitems.data(), h->bitems.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_brow_base, h->b_row_base.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_bnchunks, h->b_nchunks.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
+  return TVOLAP_OK;
+}
+
+int apply_batch_choice(tvolap_t* h, const BatchChoice& c) {
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  build_batch_work(h, c);
+  RC_TRY(upload_batch_work(h));
+  h->bchoice.chunk = h->b_chunk;
+  h->bchoice.vec = h->bshape.V;
+  h->bchoice.waves = h->bshape.NW;
   return TVOLAP_OK;
 }
 
@@ -414,9 +539,8 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_zero_in, (size_t)h->I * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_tune_out, (size_t)h->C * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_tune_sel, (size_t)h->K * h->C * sizeof(int32_t)));
-  HIP_TRY(h, dalloc(&h->d_barrive, (size_t)h->max_batch * h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_yblk, (size_t)h->max_batch * h->C * 4 * L * sizeof(float)));
-  HIP_TRY(h, hipMemsetAsync(h->d_barrive, 0, (size_t)h->max_batch * h->C * sizeof(int32_t), h->stream));
+  HIP_TRY(h, dalloc(&h->d_tune_bsel, (size_t)h->max_batch * h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_in_ch_ptr, (size_t)(h->I + 1) * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_in_ch, (size_t)h->C * sizeof(int32_t)));
   {
@@ -424,6 +548,10 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
     for (int k = 0; k < h->K; ++k)
       for (int c = 0; c < h->C; ++c) ts[(size_t)k * h->C + c] = k;
     HIP_TRY(h, hipMemcpy(h->d_tune_sel, ts.data(), ts.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    std::vector<int32_t> tb((size_t)h->max_batch * h->C);
+    for (int j = 0; j < h->max_batch; ++j)
+      for (int c = 0; c < h->C; ++c) tb[(size_t)j * h->C + c] = j % h->K;
+    HIP_TRY(h, hipMemcpy(h->d_tune_bsel, tb.data(), tb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     std::vector<int32_t> ptr(h->I + 1, 0), chs;
     for (int i = 0; i < h->I; ++i) {
       for (int c = 0; c < h->C; ++c)
@@ -467,6 +595,7 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
 
   MacChoice c;
   RC_TRY(apply_choice(h, c));
+  RC_TRY(apply_batch_choice(h, BatchChoice{}));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   return TVOLAP_OK;
 }
@@ -566,7 +695,6 @@ int reset_state(tvolap_t* h) {
   HIP_TRY(h, tvx::launch_fill_zero(h->d_counter, sizeof(uint64_t), h->stream));
   HIP_TRY(h, tvx::launch_fill_zero(h->d_arrive, (size_t)h->C * sizeof(int32_t), h->stream));
   HIP_TRY(h, tvx::launch_fill_zero(h->d_done, sizeof(int32_t), h->stream));
-  HIP_TRY(h, tvx::launch_fill_zero(h->d_barrive, (size_t)h->max_batch * h->C * sizeof(int32_t), h->stream));
   return TVOLAP_OK;
 }
 
@@ -708,20 +836,15 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   if (out_stride < (int64_t)n_blocks * h->L && h->C > 1)
     return fail(h, TVOLAP_EINVAL, "out_stride smaller than n_blocks * hop");
   if (slots_dev && slots_stride < h->C) return fail(h, TVOLAP_EINVAL, "slots_stride smaller than n_channels");
-  const int64_t need = (int64_t)h->max_batch * h->n_rows * h->tile_width;
-  if (h->bypart_elems < need) {
-    if (h->capturing) return fail(h, TVOLAP_ESTATE, "batch buffers must be allocated before graph capture");
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    dfree(h->d_bypart);
-    HIP_TRY(h, dalloc(&h->d_bypart, (size_t)need * sizeof(float2)));
-    h->bypart_elems = need;
-  }
   BatchArgs B;
   B.P = h->plan();
-  B.items = h->d_items + h->n_spec;
-  B.n_mac = h->n_mac;
+  B.items = h->d_bitems;
+  B.n_mac = h->n_bmac;
   B.n_blocks = n_blocks;
-  B.n_rows = h->n_rows;
+  B.n_rows = h->n_brows;
+  B.tile_width = h->b_tile_width;
+  B.row_base = h->d_brow_base;
+  B.nchunks = h->d_bnchunks;
   B.bank = h->d_bank;
   B.fdl = h->d_fdl;
   B.sel = slots_dev ? slots_dev : h->d_sel;
@@ -729,13 +852,12 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   B.sel_store = h->d_sel;
   B.copy_sel = slots_dev ? 1 : 0;
   B.ypart = h->d_bypart;
-  B.arrive = h->d_barrive;
-  B.needed = h->d_needed_mac;
   B.yblk = h->d_yblk;
   B.ola_state = h->d_ola;
   B.done = h->d_done;
   B.counter = h->d_counter;
-  const int grid = n_blocks * h->n_mac;
+  const int groups = ((n_blocks + 1) / 2 + tvx::kTimeBlock - 1) / tvx::kTimeBlock;
+  const int grid = h->n_bmac * 2 * groups;
   TimingSet* ts = nullptr;
   if (h->timing && !h->capturing) {
     ts = &h->tsets[h->tnext];
@@ -744,7 +866,7 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
     ts->mode = 0;          // three phases: spectra, MAC, overlap-add
     ts->blocks = n_blocks;
   }
-  HIP_TRY(h, tvx::launch_batch(B, h->dtype, h->shape, grid, in, in_stride, h->d_hist, h->d_ola, out, out_stride,
+  HIP_TRY(h, tvx::launch_batch(B, h->dtype, h->bshape, grid, in, in_stride, h->d_hist, h->d_ola, out, out_stride,
                                h->stream, ts ? ts->ev : nullptr));
   if (ts) ts->pending = true;
   return TVOLAP_OK;
@@ -767,6 +889,124 @@ int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, i
   c.waves = waves == 0 ? 4 : waves;
   c.grid = grid;
   return apply_choice(h, c);
+}
+
+int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves) {
+  if (!h) return TVOLAP_EINVAL;
+  if (h->capturing) return fail(h, TVOLAP_ESTATE, "cannot reconfigure during graph capture");
+  if (chunk < 0) return fail(h, TVOLAP_EINVAL, "chunk must be >= 0");
+  if (vec != 0 && vec != 1 && vec != 2) return fail(h, TVOLAP_EINVAL, "vec must be 0, 1 or 2");
+  if (waves != 0 && waves != 1 && waves != 2 && waves != 4) return fail(h, TVOLAP_EINVAL, "waves must be 0, 1, 2 or 4");
+  BatchChoice c;
+  c.chunk = chunk;
+  c.vec = vec;
+  c.waves = waves;
+  return apply_batch_choice(h, c);
+}
+
+int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
+  if (!h) return TVOLAP_EINVAL;
+  if (h->capturing) return fail(h, TVOLAP_ESTATE, "cannot autotune during graph capture");
+  if (iters < 1) return fail(h, TVOLAP_EINVAL, "iters must be >= 1");
+  const std::string key = "batch/" + std::to_string(h->max_batch) + "/" + tune_key(h);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_btune_cache.find(key);
+    if (it != g_btune_cache.end()) {
+      RC_TRY(apply_batch_choice(h, it->second));
+      if (best_us) *best_us = -1.f;
+      return reset_state(h);
+    }
+  }
+  const int N = 2 * h->L;
+  const int nb = h->max_batch;
+  // candidate chunks: about 1/2 to 8 workgroups per compute unit for a full batch
+  int64_t units = 0;
+  {
+    std::vector<int> maxM(h->I, 0);
+    for (int c = 0; c < h->C; ++c) maxM[h->ch_input[c]] = std::max(maxM[h->ch_input[c]], h->ch_M[c]);
+    for (int i = 0; i < h->I; ++i) units += maxM[i];
+  }
+  const int tgroups = 2 * (((nb + 1) / 2 + tvx::kTimeBlock - 1) / tvx::kTimeBlock);
+  // zero input and scratch output of one full batch, for the timing only
+  float* tin = nullptr;
+  float* tout = nullptr;
+  HIP_TRY(h, dalloc(&tin, (size_t)h->I * nb * h->L * sizeof(float)));
+  if (dalloc(&tout, (size_t)h->C * nb * h->L * sizeof(float)) != hipSuccess) {
+    dfree(tin);
+    return fail(h, TVOLAP_ENOMEM, "autotuner buffers");
+  }
+  if (tvx::launch_fill_zero(tin, (size_t)h->I * nb * h->L * sizeof(float), h->stream) != hipSuccess) {
+    dfree(tin);
+    dfree(tout);
+    return fail(h, TVOLAP_EDEVICE, "autotuner buffers");
+  }
+  const int64_t ist = (int64_t)nb * h->L;
+  hipEvent_t e0, e1;
+  HIP_TRY(h, hipEventCreate(&e0));
+  HIP_TRY(h, hipEventCreate(&e1));
+  const bool timing_was = h->timing;
+  h->timing = false;
+  BatchChoice best;
+  float best_t = 1e30f;
+  int rc = TVOLAP_OK;
+  const std::vector<int> vecs = {1, 2};
+  for (int vec : vecs) {
+    for (int nw : {1, 2, 4}) {
+      if (64 * vec * nw > N) continue;
+      const int tiles = N / (64 * vec * nw);
+      std::vector<int> chunks;
+      for (int half_per_cu : {1, 2, 4, 8, 16}) {
+        const int64_t target = (int64_t)half_per_cu * h->n_cu / 2;
+        const int64_t work = units * tiles * tgroups;
+        const int S = (int)std::max<int64_t>(2, (work + target - 1) / target);
+        if (std::find(chunks.begin(), chunks.end(), S) == chunks.end()) chunks.push_back(S);
+      }
+      for (int S : chunks) {
+        BatchChoice c;
+        c.chunk = S;
+        c.vec = vec;
+        c.waves = nw;
+        rc = apply_batch_choice(h, c);
+        if (rc != TVOLAP_OK) break;
+        // every block of the batch selects slot (block mod K), as a switching stream does
+        rc = tvolap_process_blocks(h, tin, ist, nb, tout, ist, h->d_tune_bsel, h->C);
+        if (rc != TVOLAP_OK) break;
+        if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = fail(h, TVOLAP_EDEVICE, "event record"); break; }
+        for (int k = 0; k < iters && rc == TVOLAP_OK; ++k)
+          rc = tvolap_process_blocks(h, tin, ist, nb, tout, ist, h->d_tune_bsel, h->C);
+        if (rc != TVOLAP_OK) break;
+        if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(h, TVOLAP_EDEVICE, "event synchronize");
+          break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const float us = 1e3f * ms / (float)(iters * nb);
+        if (us < best_t) {
+          best_t = us;
+          best = h->bchoice;
+        }
+      }
+      if (rc != TVOLAP_OK) break;
+    }
+    if (rc != TVOLAP_OK) break;
+  }
+  if (rc == TVOLAP_OK && best_t >= 1e30f) rc = fail(h, TVOLAP_EDEVICE, "autotuner found no candidate");
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dfree(tin);
+  dfree(tout);
+  h->timing = timing_was;
+  if (rc != TVOLAP_OK) return rc;
+  RC_TRY(apply_batch_choice(h, best));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_btune_cache[key] = best;
+  }
+  if (best_us) *best_us = best_t;
+  return reset_state(h);
 }
 
 int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us) {
@@ -931,6 +1171,12 @@ int tvolap_get_info(const tvolap_t* h, tvolap_info* info) {
   info->mac_waves = h->shape.NW;
   info->mac_grid = grid_of(h);
   info->fused = h->choice.fused;
+  info->batch_chunk = h->b_chunk;
+  info->batch_vec = h->bshape.V;
+  info->batch_waves = h->bshape.NW;
+  info->batch_tile_width = h->b_tile_width;
+  info->batch_work_items = h->n_bmac;
+  info->batch_rows = h->n_brows;
   info->n_cu = h->n_cu;
   return TVOLAP_OK;
 }

@@ -63,6 +63,9 @@ struct BlockArgs {
   int32_t inverse_inline;      // 1: last item of a channel transforms back; 0: a later kernel does
 };
 
+// Blocks of one parity per time-blocked MAC item in batched calls.
+constexpr int kTimeBlock = 8;
+
 struct MacShape {
   int32_t V;    // complex bins per lane (tile width = 64 V)
   int32_t G;    // channel capacity of a work item (1, 2 or 4)
@@ -80,13 +83,17 @@ hipError_t launch_inv(const DevPlan& P, int dtype, const float2* ypart, const vo
                       int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s);
 hipError_t launch_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s);
 
-// Batches of consecutive blocks (see k_batch_* in tvolap_kernels.hip).
+// Batches of consecutive blocks (k_batch_spectra, k_tmac, k_batch_inv,
+// k_batch_ola in tvolap_kernels.hip).
 struct BatchArgs {
   DevPlan P;
-  const WorkItem* items;       // MAC items of one block
+  const WorkItem* items;       // time-blocked MAC items (partitions from 0)
   int32_t n_mac;
   int32_t n_blocks;
   int32_t n_rows;              // partial rows of one block
+  int32_t tile_width;          // bins per item tile (64 V NW)
+  const int32_t* row_base;     // [C] first partial row of channel c (rows ordered tile, chunk)
+  const int32_t* nchunks;      // [C] partition chunks of channel c
   const void* bank;
   void* fdl;
   const int32_t* sel;          // [n_blocks][sel_stride] slots (caller's or the handle's with stride 0)
@@ -94,20 +101,37 @@ struct BatchArgs {
   int32_t* sel_store;
   int32_t copy_sel;
   float2* ypart;               // [n_max][rows][tile_width]
-  int32_t* arrive;             // [n_max][C]
-  const int32_t* needed;       // [C] MAC items per channel
   float* yblk;                 // [n_max][C][4L]
   float* ola_state;            // [C][3L]
   int32_t* done;
   uint64_t* counter;
 };
 // ev (may be NULL): four events recorded before the spectra, before the MAC,
-// before the overlap-add and after it.
+// after the MAC and after the overlap-add.
 hipError_t launch_batch(const BatchArgs& B, int dtype, const MacShape& shape, int grid, const float* in,
                         int64_t in_stride, float* hist, float* ola, float* out, int64_t out_stride, hipStream_t s,
                         hipEvent_t* ev);
 hipError_t launch_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M,
                          void* dst, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// The same launchers for one hop L, instantiated by the kernel file compiled
+// for that hop; launch_fwd and the others above pick one by P.L.
+template <int L>
+hipError_t hop_fwd(const DevPlan& P, int dtype, const float* in, int64_t in_stride, float* hist, void* fdl,
+                   const uint64_t* counter, hipStream_t s);
+template <int L>
+hipError_t hop_inv(const DevPlan& P, int dtype, const float2* ypart, const void* bank, const void* fdl,
+                   const int32_t* sel, float* ola, float* out, int64_t out_stride, int32_t copy_sel,
+                   int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s);
+template <int L>
+hipError_t hop_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s);
+template <int L>
+hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int grid, const float* in,
+                     int64_t in_stride, float* hist, float* ola, float* out, int64_t out_stride, hipStream_t s,
+                     hipEvent_t* ev);
+template <int L>
+hipError_t hop_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M, void* dst,
+                      hipStream_t s);
 
 }  // namespace tvx

@@ -19,9 +19,15 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "fft_lds.hpp"
 #include "tvolap_internal.h"
+
+#ifndef TVX_HOP
+#error "compile once per hop with -DTVX_HOP=64, 128, 256 or 512"
+#endif
+static_assert(TVX_HOP == 64 || TVX_HOP == 128 || TVX_HOP == 256 || TVX_HOP == 512, "unsupported hop");
 
 namespace tvx {
 namespace {
@@ -72,7 +78,9 @@ template <> __device__ __forceinline__ float2 unpack<2>(uint32_t w) {
 // Load V consecutive stored complex values (16 bytes per lane where possible).
 template <int DT, int V>
 __device__ __forceinline__ void load_vec(const typename Store<DT>::T* __restrict__ p, float2 (&o)[V]) {
-  if constexpr (DT == 0) {
+  if constexpr (DT == 0 && V == 1) {
+    o[0] = p[0];
+  } else if constexpr (DT == 0) {
 #pragma unroll
     for (int j = 0; j < V; j += 2) {
       const float4 t = *reinterpret_cast<const float4*>(p + j);
@@ -81,7 +89,9 @@ __device__ __forceinline__ void load_vec(const typename Store<DT>::T* __restrict
     }
   } else {
     uint32_t w[V];
-    if constexpr (V == 2) {
+    if constexpr (V == 1) {
+      w[0] = p[0];
+    } else if constexpr (V == 2) {
       const uint2 t = *reinterpret_cast<const uint2*>(p);
       w[0] = t.x; w[1] = t.y;
     } else {
@@ -546,116 +556,404 @@ __global__ __launch_bounds__(256) void k_batch_spectra(DevPlan P, const float* _
   for (int k = tid; k < N; k += T) dst[k] = pack<DT>(fft::real_fwd_post<N>(Z, k, twl));
 }
 
-// MAC items of all blocks of the batch (block-major order). The last item to
-// finish a (block, channel) pair writes that block's 4L output samples.
-template <int L, int V, int G, int NW, int DT>
-__global__ __launch_bounds__(64 * NW) void k_batch_mac(BatchArgs B) {
+// Spectral MAC of a batch (eq. 8), blocked in time. Blocks of one parity
+// read the same delay-line ring: block l + 2 at partition m + 1 reads the
+// spectrum that block l reads at partition m, and blocks that use the same IR
+// slot read the same partition spectra. An item covers (up to G channels of
+// one input, a bin tile, partitions [m0, m1)) for up to TB blocks of one
+// parity; each wave owns 64 V bins of the tile and walks the partitions in
+// order, keeping the TB delay-line rows of the current partition in a
+// circular register buffer (one new row per partition) and loading each
+// partition spectrum once per distinct slot. Every (block, channel) gets one
+// partial spectrum row per partition chunk.
+
+// Slot pattern of an item's blocks, per channel: one slot for all blocks,
+// two slots alternating with the block index, or any assignment of up to two
+// slots per pass (blocks of further slots take further passes).
+enum TmacPattern { kOneSlot = 1, kAlternating = 2, kSelect = 3 };
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// f(integral_constant<int, i>) for i = 0 .. n-1, unrolled at compile time.
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int n, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, n>{});
+}
+
+template <int L, int V, int G, int TB, int DT>
+__global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
   using ST = typename Store<DT>::T;
   constexpr int N = 2 * L;
-  constexpr int T = 64 * NW;
-  constexpr int TW = 64 * V;
-  __shared__ float2 twl[2 * N];
-  __shared__ float winl[N];
-  __shared__ float2 bufA[N];
-  __shared__ float2 bufB[N];
-  __shared__ float2 ybuf[N];
-  __shared__ float2 red[NW][G][TW];
-  __shared__ int flag;
+  const int TW = B.tile_width;   // 64 V bins per wave, blockDim.x / 64 waves
+  constexpr int PD = 2;   // partitions loaded ahead
   const DevPlan& P = B.P;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int w = tid >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
   const uint64_t cnt0 = *B.counter;
+  const int n = B.n_blocks;
+  const int groups = ((n + 1) / 2 + TB - 1) / TB;     // time groups per parity class
+  const int total = B.n_mac * 2 * groups;
   const ST* bank = static_cast<const ST*>(B.bank);
   const ST* fdl = static_cast<const ST*>(B.fdl);
-  load_tables<L, T>(P, twl, winl, tid);
-  const int total = B.n_blocks * B.n_mac;
   for (int idx = blockIdx.x; idx < total; idx += gridDim.x) {
-    const int j = idx / B.n_mac;
-    const WorkItem it = B.items[idx - j * B.n_mac];
-    const uint64_t cnt = cnt0 + (uint64_t)j;
-    const int p = (int)(cnt & 1u);
-    const int32_t* sel = B.sel + (int64_t)j * B.sel_stride;
-    float2* ypart = B.ypart + (int64_t)j * B.n_rows * TW;
-    int32_t* arrive = B.arrive + (int64_t)j * P.C;
-    float2 acc[G][V];
-    mac_item<V, G, NW, DT, 2>(P, it, bank, fdl, sel, p, cnt, lane, w, acc);
-    write_partials<V, G, NW, true>(it, acc, red, ypart, lane, w, tid);
-    wait_memory();
-    __syncthreads();
+    const int tg = idx / B.n_mac;
+    const WorkItem it = B.items[idx - tg * B.n_mac];
+    const int j0 = (tg & 1) + 2 * TB * (tg >> 1);       // first block of the group
+    if (j0 >= n) continue;
+    const int nb = min(TB, (n - j0 + 1) / 2);            // blocks j0, j0 + 2, ...
+    const int i = uniform(it.input);
+    const int n_ch = uniform(it.n_ch);
+    const int m0 = uniform(it.m0), m1 = uniform(it.m1);
+    const int Mi = uniform(P.in_M[i]);
+    const uint64_t c0 = cnt0 + (uint64_t)j0;
+    const int p = (int)(c0 & 1u);
+    const int q0 = ring_slot(c0, Mi);
+    const uint32_t kb = (uint32_t)(it.tile * TW + w * 64 * V + lane * V);
+    const ST* xbase = fdl + P.in_fdl_off[i] + (int64_t)p * Mi * N;
+    int Mc[G], McL[G], ch[G];
+    const ST* hch[G];
+    int slot[G][TB];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      if (g < it.n_ch) {
-        const int c = it.ch[g];
-        if (tid == 0) flag = (atomicAdd(&arrive[c], 1) == B.needed[c] - 1) ? 1 : 0;
-        __syncthreads();
-        if (flag) {
-          channel_spectrum<L, T, DT, true>(P, ypart, bank, fdl, sel, c, p, cnt, ybuf, tid);
-          __syncthreads();
-          inverse_store<L, T>(ybuf, bufA, bufB, twl, B.yblk + ((int64_t)j * P.C + c) * 4 * L, tid);
-          if (tid == 0) arrive[c] = 0;
+      ch[g] = uniform(g < n_ch ? it.ch[g] : it.ch[0]);
+      McL[g] = uniform(P.ch_M[ch[g]]);
+      Mc[g] = g < n_ch ? McL[g] : 0;
+      hch[g] = bank + P.ch_bank_off[ch[g]];
+    }
+    // slots of every block (loads issued together; block indices past the
+    // group repeat its last block)
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) slot[g][b] = B.sel[(int64_t)(j0 + 2 * min(b, nb - 1)) * B.sel_stride + ch[g]];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int sv = uniform(slot[g][b]);
+        slot[g][b] = sv < 0 ? 0 : (sv >= P.K ? P.K - 1 : sv);
+      }
+    bool one = true, alt = true;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        one = one && (slot[g][b] == slot[g][0]);
+        alt = alt && (slot[g][b] == slot[g][b & 1]);
+      }
+    float2 acc[G][TB][V];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int b = 0; b < TB; ++b)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[g][b][v] = make_float2(0.f, 0.f);
+
+    const bool dcw = (it.tile == 0 && w == 0);   // this wave holds the packed DC / Nyquist bin
+    const bool dc_lane = dcw && lane == 0;
+    int mlast[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) mlast[g] = min(m1, McL[g]) - 1;
+
+    // The partition loop for one slot pattern. X: circular buffer of the TB
+    // delay-line rows of the current partition (block b at partition m0 + t
+    // is in X[(b - t) mod TB]); Hq / Xq: ring of PD partitions' spectra and
+    // next rows, loaded ahead of use.
+    auto run = [&](auto patc, auto dcwc, const ST* const (&hr)[G][2], const uint32_t (&sel1)[G],
+                   const uint32_t (&take)[G]) {
+      constexpr int PAT = decltype(patc)::value;
+      constexpr bool DCW = decltype(dcwc)::value;
+      constexpr int ND = (PAT == kOneSlot) ? 1 : 2;
+      float2 X[TB][V];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        int r = q0 + min(b, nb - 1) - m0;
+        r = r < 0 ? r + Mi : (r >= Mi ? r - Mi : r);
+        load_vec<DT, V>(xbase + (uint32_t)r * N + kb, X[b]);
+      }
+      float2 Hq[PD][G][ND][V];
+      float2 Xq[PD][V];
+      auto load_h = [&](float2 (&Hs)[G][ND][V], int mm) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int mr = min(mm, mlast[g]);
+#pragma unroll
+          for (int d = 0; d < ND; ++d) load_vec<DT, V>(hr[g][d] + (uint32_t)mr * N + kb, Hs[g][d]);
         }
-        __syncthreads();
+      };
+      auto load_x = [&](float2 (&Xs)[V], int mm) {   // delay-line row of partition mm for block 0
+        int r = q0 - min(mm, m1 - 1);
+        r = r < 0 ? r + Mi : r;
+        load_vec<DT, V>(xbase + (uint32_t)r * N + kb, Xs);
+      };
+      // partition mm = m0 + t (t = step index): accumulate, using X rows at
+      // circular offset t
+      auto step = [&](const float2 (&Hs)[G][ND][V], int mm, auto tc) {
+        constexpr int T0 = decltype(tc)::value;   // t mod TB
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if (mm < Mc[g]) {
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+#pragma unroll
+              for (int v = 0; v < V; ++v) {
+                const float2 h = Hs[g][d][v];
+                // complex product terms; on the DC lane (packed Re X(0),
+                // Re X(2L)) the product is component-wise
+                float hx = h.x, hny = -h.y, hx2 = h.x, hy2 = h.y;
+                if (DCW && v == 0) {
+                  hny = dc_lane ? 0.f : -h.y;
+                  hx2 = dc_lane ? h.y : h.x;
+                  hy2 = dc_lane ? 0.f : h.y;
+                }
+#pragma unroll
+                for (int b = 0; b < TB; ++b) {
+                  bool use;
+                  if constexpr (PAT == kOneSlot) use = true;
+                  else if constexpr (PAT == kAlternating) use = ((b & 1) == d);
+                  else use = true;
+                  if (use) {
+                    const float2 x = X[(b - T0 + TB) % TB][v];
+                    if constexpr (PAT == kSelect) {
+                      // uniform per (g, b): slot d of this pass, or nothing
+                      const bool on = ((take[g] >> b) & 1u) && ((((sel1[g] >> b) & 1u) != 0u) == (d == 1));
+                      if (on) {
+                        acc[g][b][v].x = fmaf(hx, x.x, acc[g][b][v].x);
+                        acc[g][b][v].x = fmaf(hny, x.y, acc[g][b][v].x);
+                        acc[g][b][v].y = fmaf(hx2, x.y, acc[g][b][v].y);
+                        acc[g][b][v].y = fmaf(hy2, x.x, acc[g][b][v].y);
+                      }
+                    } else {
+                      acc[g][b][v].x = fmaf(hx, x.x, acc[g][b][v].x);
+                      acc[g][b][v].x = fmaf(hny, x.y, acc[g][b][v].x);
+                      acc[g][b][v].y = fmaf(hx2, x.y, acc[g][b][v].y);
+                      acc[g][b][v].y = fmaf(hy2, x.x, acc[g][b][v].y);
+                    }
+                  }
+                }
+              }
+            }
+          }
+        }
+      };
+#pragma unroll
+      for (int st = 0; st < PD; ++st) {
+        load_h(Hq[st], m0 + st);
+        load_x(Xq[st], m0 + st + 1);
+      }
+      // one partition: accumulate, then load the spectra PD partitions ahead
+      // and move the prefetched row of partition mm + 1 (block 0) to where
+      // block TB - 1's row of partition mm was
+      auto advance = [&](int mm, auto tc) {
+        constexpr int t = decltype(tc)::value;
+        step(Hq[t % PD], mm, tc);
+        load_h(Hq[t % PD], mm + PD);
+#pragma unroll
+        for (int v = 0; v < V; ++v) X[(TB - 1 - t) % TB][v] = Xq[t % PD][v];
+        load_x(Xq[t % PD], mm + 1 + PD);
+      };
+      int mb = m0;
+      for (; mb + TB <= m1; mb += TB) static_for<TB>([&](auto tc) { advance(mb + decltype(tc)::value, tc); });
+      static_for<TB>([&](auto tc) {
+        if (mb + decltype(tc)::value < m1) advance(mb + decltype(tc)::value, tc);
+      });
+    };
+
+    if (one || alt) {
+      const ST* hr[G][2];
+      uint32_t none[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        none[g] = 0u;
+        hr[g][0] = hch[g] + (int64_t)slot[g][0] * McL[g] * N;
+        hr[g][1] = hch[g] + (int64_t)slot[g][1] * McL[g] * N;
+      }
+      if (one) {
+        if (dcw) run(std::integral_constant<int, kOneSlot>{}, std::true_type{}, hr, none, none);
+        else run(std::integral_constant<int, kOneSlot>{}, std::false_type{}, hr, none, none);
+      } else {
+        if (dcw) run(std::integral_constant<int, kAlternating>{}, std::true_type{}, hr, none, none);
+        else run(std::integral_constant<int, kAlternating>{}, std::false_type{}, hr, none, none);
+      }
+    } else {
+      // passes of up to two slots per channel
+      uint32_t todo[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) todo[g] = (g < n_ch) ? ((1u << nb) - 1u) : 0u;
+      while (true) {
+        bool any = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) any = any || (todo[g] != 0u);
+        if (!any) break;
+        const ST* hr[G][2];
+        uint32_t sel1[G], take[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          uint32_t mk[2] = {0u, 0u};
+          int sl[2] = {0, 0};
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            if (todo[g] != 0u) {
+              const int first = __builtin_ctz(todo[g]);
+              int sv = 0;
+#pragma unroll
+              for (int b = 0; b < TB; ++b)
+                if (b == first) sv = slot[g][b];
+#pragma unroll
+              for (int b = 0; b < TB; ++b)
+                if (((todo[g] >> b) & 1u) && slot[g][b] == sv) mk[d] |= 1u << b;
+              todo[g] &= ~mk[d];
+              sl[d] = sv;
+            } else {
+              sl[d] = sl[0];
+            }
+          }
+          sel1[g] = mk[1];
+          take[g] = mk[0] | mk[1];
+          hr[g][0] = hch[g] + (int64_t)sl[0] * McL[g] * N;
+          hr[g][1] = hch[g] + (int64_t)sl[1] * McL[g] * N;
+        }
+        if (dcw) run(std::integral_constant<int, kSelect>{}, std::true_type{}, hr, sel1, take);
+        else run(std::integral_constant<int, kSelect>{}, std::false_type{}, hr, sel1, take);
+      }
+    }
+    // partial rows: block j0 + 2b, channel g
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (g < n_ch) {
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+          if (b < nb) {
+            float2* dst = B.ypart + ((int64_t)(j0 + 2 * b) * B.n_rows + it.row[g]) * TW + w * 64 * V + lane * V;
+            if constexpr (V == 1) {
+              dst[0] = acc[g][b][0];
+            } else {
+#pragma unroll
+              for (int v = 0; v < V; v += 2)
+                *reinterpret_cast<float4*>(dst + v) =
+                    make_float4(acc[g][b][v].x, acc[g][b][v].y, acc[g][b][v + 1].x, acc[g][b][v + 1].y);
+            }
+          }
+        }
       }
     }
   }
 }
 
-// One workgroup per channel (and per input for the history): overlap-add the
-// batch's blocks in call order, carry the state, store the last history, and
-// advance the call count by n once every workgroup has read it.
+// Block j, channel c of a batch: the sum of the channel's partial rows (all
+// partitions, eq. 8) and the inverse transform (eq. 9) into the block buffer.
+template <int L>
+__global__ __launch_bounds__(256) void k_batch_inv(BatchArgs B) {
+  constexpr int N = 2 * L;
+  constexpr int T = 256;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
+  __shared__ float2 Y[N];
+  __shared__ float2 bufA[N];
+  __shared__ float2 bufB[N];
+  const DevPlan& P = B.P;
+  const int c = blockIdx.x, j = blockIdx.y, tid = threadIdx.x;
+  load_tables<L, T>(P, twl, winl, tid);
+  const int TW = B.tile_width;
+  const int base = B.row_base[c];
+  const int nch = B.nchunks[c];
+  const float2* yp = B.ypart + (int64_t)j * B.n_rows * TW;
+  for (int k = tid; k < N; k += T) {
+    const int t = k / TW;
+    const int kk = k - t * TW;
+    const float2* src = yp + ((int64_t)base + (int64_t)t * nch) * TW + kk;
+    float2 s0 = src[0];
+    float2 s1 = make_float2(0.f, 0.f);
+    int q = 1;
+    for (; q + 1 < nch; q += 2) {
+      s0 = cadd(s0, src[(int64_t)q * TW]);
+      s1 = cadd(s1, src[(int64_t)(q + 1) * TW]);
+    }
+    if (q < nch) s0 = cadd(s0, src[(int64_t)q * TW]);
+    Y[k] = cadd(s0, s1);
+  }
+  __syncthreads();
+  inverse_store<L, T>(Y, bufA, bufB, twl, B.yblk + ((int64_t)j * P.C + c) * 4 * L, tid);
+}
+
+// One workgroup per channel (and per input for the history): overlap-add of
+// the batch's n blocks (eq. 10-13 in the two-step form). Emitted window j of
+// the batch (samples jL .. jL+L) is the carried state for j < 3 plus the
+// quarter d of block j - d for d = 0..3; the new carried state (3L samples)
+// is what reaches past the last window. Every block sample is read once, and
+// all windows are independent, so the whole batch is one parallel pass; the
+// old state is staged in LDS so that it can be overwritten in place. The
+// workgroups advance the call count by n once every one of them has read it.
 template <int L>
 __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __restrict__ in, int64_t in_stride,
                                                    float* __restrict__ hist, float* __restrict__ ola,
                                                    float* __restrict__ out, int64_t out_stride) {
   constexpr int T = 256;
-  constexpr int NPT = (4 * L + T - 1) / T;
   const DevPlan& P = B.P;
   const int c = blockIdx.x, tid = threadIdx.x;
+  const int n = B.n_blocks;
   const uint64_t cnt0 = *B.counter;
   if (c < P.C) {
+    __shared__ float st_old[3 * L];
     float* st = ola + (int64_t)c * 3 * L;
-    float acc[NPT];   // acc[j] holds state(n), n = tid + j T (n < 3L), for the next block
+    for (int u = tid; u < 3 * L; u += T) st_old[u] = st[u];
+    __syncthreads();
+    const float* yc = B.yblk + (int64_t)c * 4 * L;     // block j at yc + j * C * 4L
+    const int64_t ystride = (int64_t)P.C * 4 * L;
+    float* oc = out + (int64_t)c * out_stride;
+    // emitted samples t = jL + k, j < n; eight per thread at a time, all
+    // loads issued before the stores
+    constexpr int R = 8;
+    for (int t0 = 0; t0 < n * L; t0 += R * T) {
+      float v[R];
 #pragma unroll
-    for (int q = 0; q < NPT; ++q) {
-      const int n = tid + q * T;
-      acc[q] = (n < 3 * L) ? st[n] : 0.f;
-    }
-    __shared__ float sh[4 * L];
-    for (int j = 0; j < B.n_blocks; ++j) {
-      const float* y = B.yblk + ((int64_t)j * P.C + c) * 4 * L;
-      float* o = out + (int64_t)c * out_stride + (int64_t)j * L;
+      for (int r = 0; r < R; ++r) {
+        const int t = t0 + r * T + tid;
+        v[r] = 0.f;
+        if (t < n * L) {
+          const int j = t / L, k = t - j * L;
+          float a = (j < 3) ? st_old[j * L + k] : 0.f;
+          // oldest block first: the order in which one-block calls accumulate
 #pragma unroll
-      for (int q = 0; q < NPT; ++q) {
-        const int n = tid + q * T;
-        if (n < 4 * L) sh[n] = acc[q] + y[n];   // state(n) + y(n); state(n) = 0 for n >= 3L
+          for (int d = 3; d >= 0; --d)
+            if (j - d >= 0) a += yc[(int64_t)(j - d) * ystride + d * L + k];
+          v[r] = a;
+        }
       }
-      __syncthreads();
 #pragma unroll
-      for (int q = 0; q < NPT; ++q) {
-        const int n = tid + q * T;
-        if (n < L) o[n] = sh[n];
-        acc[q] = (n < 3 * L) ? sh[n + L] : 0.f;   // shift by L
+      for (int r = 0; r < R; ++r) {
+        const int t = t0 + r * T + tid;
+        if (t < n * L) oc[t] = v[r];
       }
-      __syncthreads();
     }
+    // new carried state u = qL + k: windows n + q, q < 3
+    for (int u = tid; u < 3 * L; u += T) {
+      const int q = u / L, k = u - q * L;
+      float v = (n + q < 3) ? st_old[(n + q) * L + k] : 0.f;
 #pragma unroll
-    for (int q = 0; q < NPT; ++q) {
-      const int n = tid + q * T;
-      if (n < 3 * L) st[n] = acc[q];
+      for (int d = 3; d >= 1; --d) {
+        const int j = n + q - d;
+        if (d > q && j >= 0) v += yc[(int64_t)j * ystride + d * L + k];
+      }
+      st[u] = v;
     }
-    if (tid == 0 && B.copy_sel) B.sel_store[c] = B.sel[(int64_t)(B.n_blocks - 1) * B.sel_stride + c];
+    if (tid == 0 && B.copy_sel) B.sel_store[c] = B.sel[(int64_t)(n - 1) * B.sel_stride + c];
   }
   if (c < P.I) {
-    const uint64_t last = cnt0 + (uint64_t)(B.n_blocks - 1);
+    const uint64_t last = cnt0 + (uint64_t)(n - 1);
     float* hnew = hist + ((size_t)(last & 1u) * P.I + c) * L;
-    const float* xin = in + (int64_t)c * in_stride + (int64_t)(B.n_blocks - 1) * L;
-    for (int n = tid; n < L; n += T) hnew[n] = xin[n];
+    const float* xin = in + (int64_t)c * in_stride + (int64_t)(n - 1) * L;
+    for (int k = tid; k < L; k += T) hnew[k] = xin[k];
   }
+  __syncthreads();
   if (tid == 0) {
     if (atomicAdd(B.done, 1) == (int)gridDim.x - 1) {
       *B.done = 0;
-      *B.counter = cnt0 + (uint64_t)B.n_blocks;
+      *B.counter = cnt0 + (uint64_t)n;
     }
   }
 }
@@ -762,17 +1060,6 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint4* __restrict__ p, size_t
 // ---------------------------------------------------------------- dispatch
 
 template <typename F>
-hipError_t by_hop(int L, F&& f) {
-  switch (L) {
-    case 64: return f(std::integral_constant<int, 64>{});
-    case 128: return f(std::integral_constant<int, 128>{});
-    case 256: return f(std::integral_constant<int, 256>{});
-    case 512: return f(std::integral_constant<int, 512>{});
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <typename F>
 hipError_t by_dtype(int dt, F&& f) {
   switch (dt) {
     case 0: return f(std::integral_constant<int, 0>{});
@@ -806,20 +1093,131 @@ hipError_t by_shape(const MacShape& sh, F&& f) {
   }
 }
 
+// Batched MAC shapes: V in {1, 2} bins per lane, G in {1, 2} channels per
+// item (the waves per tile, 1, 2 or 4, are a launch parameter).
+template <typename F>
+hipError_t by_bshape(const MacShape& sh, F&& f) {
+  auto g = [&](auto V) -> hipError_t {
+    switch (sh.G) {
+      case 1: return f(V, std::integral_constant<int, 1>{});
+      case 2: return f(V, std::integral_constant<int, 2>{});
+      default: return hipErrorInvalidValue;
+    }
+  };
+  switch (sh.V) {
+    case 1: return g(std::integral_constant<int, 1>{});
+    case 2: return g(std::integral_constant<int, 2>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
-hipError_t launch_fwd(const DevPlan& P, int dtype, const float* in, int64_t in_stride, float* hist, void* fdl,
-                      const uint64_t* counter, hipStream_t s) {
-  return by_hop(P.L, [&](auto Lc) {
-    return by_dtype(dtype, [&](auto Dc) {
-      constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value;
-      hipLaunchKernelGGL((k_fwd<L, DT>), dim3(P.I), dim3(64), 0, s, P, in, in_stride, hist,
-                         static_cast<typename Store<DT>::T*>(fdl), counter);
-      return hipGetLastError();
+// Launchers that depend on the hop L. This file is compiled once per hop
+// (TVX_HOP) and instantiates them for that hop only; the hop-independent
+// launchers are compiled with the smallest hop.
+
+template <int L>
+hipError_t hop_fwd(const DevPlan& P, int dtype, const float* in, int64_t in_stride, float* hist, void* fdl,
+                   const uint64_t* counter, hipStream_t s) {
+  return by_dtype(dtype, [&](auto Dc) {
+    constexpr int DT = decltype(Dc)::value;
+    hipLaunchKernelGGL((k_fwd<L, DT>), dim3(P.I), dim3(64), 0, s, P, in, in_stride, hist,
+                       static_cast<typename Store<DT>::T*>(fdl), counter);
+    return hipGetLastError();
+  });
+}
+
+template <int L>
+hipError_t hop_inv(const DevPlan& P, int dtype, const float2* ypart, const void* bank, const void* fdl,
+                   const int32_t* sel, float* ola, float* out, int64_t out_stride, int32_t copy_sel,
+                   int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s) {
+  return by_dtype(dtype, [&](auto Dc) {
+    constexpr int DT = decltype(Dc)::value;
+    using ST = typename Store<DT>::T;
+    hipLaunchKernelGGL((k_inv<L, DT>), dim3(P.C), dim3(64), 0, s, P, ypart, static_cast<const ST*>(bank),
+                       static_cast<const ST*>(fdl), sel, ola, out, out_stride, copy_sel, sel_store, done, counter);
+    return hipGetLastError();
+  });
+}
+
+template <int L>
+hipError_t hop_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s) {
+  if (A.n_items <= 0 || grid <= 0) return hipErrorInvalidValue;
+  return by_dtype(dtype, [&](auto Dc) {
+    return by_shape(shape, [&](auto Vc, auto Gc, auto NWc) {
+      constexpr int DT = decltype(Dc)::value, V = decltype(Vc)::value, G = decltype(Gc)::value,
+                    NW = decltype(NWc)::value;
+      if constexpr (64 * V > 2 * L) {
+        return hipErrorInvalidValue;
+      } else {
+        hipLaunchKernelGGL((k_block<L, V, G, NW, DT>), dim3(grid), dim3(64 * NW), 0, s, A);
+        return hipGetLastError();
+      }
     });
   });
 }
 
+template <int L>
+hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int grid, const float* in,
+                     int64_t in_stride, float* hist, float* ola, float* out, int64_t out_stride, hipStream_t s,
+                     hipEvent_t* ev) {
+  if (B.n_blocks <= 0) return hipSuccess;
+  return by_dtype(dtype, [&](auto Dc) {
+    constexpr int DT = decltype(Dc)::value;
+    using ST = typename Store<DT>::T;
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_batch_spectra<L, DT>), dim3(B.n_blocks, B.P.I), dim3(256), 0, s, B.P, in, in_stride,
+                       hist, static_cast<ST*>(B.fdl), B.counter);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    if (B.n_mac > 0) {
+      e = by_bshape(shape, [&](auto Vc, auto Gc) {
+        constexpr int V = decltype(Vc)::value, G = decltype(Gc)::value;
+        if (shape.NW != 1 && shape.NW != 2 && shape.NW != 4) return hipErrorInvalidValue;
+        if (64 * V * shape.NW != B.tile_width || B.tile_width > 2 * L) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_tmac<L, V, G, kTimeBlock, DT>), dim3(grid), dim3(64 * shape.NW), 0, s, B);
+        return hipGetLastError();
+      });
+      if (e != hipSuccess) return e;
+    }
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_batch_inv<L>), dim3(B.P.C, B.n_blocks), dim3(256), 0, s, B);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int wgs = B.P.C > B.P.I ? B.P.C : B.P.I;
+    hipLaunchKernelGGL((k_batch_ola<L>), dim3(wgs), dim3(256), 0, s, B, in, in_stride, hist, B.ola_state, out,
+                       out_stride);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev) e = hipEventRecord(ev[3], s);
+    return e;
+  });
+}
+
+template <int L>
+hipError_t hop_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M, void* dst,
+                      hipStream_t s) {
+  return by_dtype(dtype, [&](auto Dc) {
+    constexpr int DT = decltype(Dc)::value;
+    hipLaunchKernelGGL((k_irprep<L, DT>), dim3(M), dim3(64), 0, s, P, taps, n_taps,
+                       static_cast<typename Store<DT>::T*>(dst));
+    return hipGetLastError();
+  });
+}
+
+template hipError_t hop_fwd<TVX_HOP>(const DevPlan&, int, const float*, int64_t, float*, void*, const uint64_t*,
+                                     hipStream_t);
+template hipError_t hop_inv<TVX_HOP>(const DevPlan&, int, const float2*, const void*, const void*, const int32_t*,
+                                     float*, float*, int64_t, int32_t, int32_t*, int32_t*, uint64_t*, hipStream_t);
+template hipError_t hop_block<TVX_HOP>(const BlockArgs&, int, const MacShape&, int, hipStream_t);
+template hipError_t hop_batch<TVX_HOP>(const BatchArgs&, int, const MacShape&, int, const float*, int64_t, float*,
+                                       float*, float*, int64_t, hipStream_t, hipEvent_t*);
+template hipError_t hop_irprep<TVX_HOP>(const DevPlan&, int, const float*, int32_t, int32_t, void*, hipStream_t);
+
+#if TVX_HOP == 64
 hipError_t launch_mac(const DevPlan& P, int dtype, const MacShape& shape, const WorkItem* items, int n_items,
                       const void* bank, const void* fdl, const int32_t* sel, float2* ypart,
                       const uint64_t* counter, hipStream_t s) {
@@ -836,89 +1234,6 @@ hipError_t launch_mac(const DevPlan& P, int dtype, const MacShape& shape, const 
   });
 }
 
-hipError_t launch_inv(const DevPlan& P, int dtype, const float2* ypart, const void* bank, const void* fdl,
-                      const int32_t* sel, float* ola, float* out, int64_t out_stride, int32_t copy_sel,
-                      int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s) {
-  return by_hop(P.L, [&](auto Lc) {
-    return by_dtype(dtype, [&](auto Dc) {
-      constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value;
-      using ST = typename Store<DT>::T;
-      hipLaunchKernelGGL((k_inv<L, DT>), dim3(P.C), dim3(64), 0, s, P, ypart, static_cast<const ST*>(bank),
-                         static_cast<const ST*>(fdl), sel, ola, out, out_stride, copy_sel, sel_store, done, counter);
-      return hipGetLastError();
-    });
-  });
-}
-
-hipError_t launch_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s) {
-  if (A.n_items <= 0 || grid <= 0) return hipErrorInvalidValue;
-  return by_hop(A.P.L, [&](auto Lc) {
-    return by_dtype(dtype, [&](auto Dc) {
-      return by_shape(shape, [&](auto Vc, auto Gc, auto NWc) {
-        constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value, V = decltype(Vc)::value,
-                      G = decltype(Gc)::value, NW = decltype(NWc)::value;
-        if constexpr (64 * V > 2 * L) {
-          return hipErrorInvalidValue;
-        } else {
-          hipLaunchKernelGGL((k_block<L, V, G, NW, DT>), dim3(grid), dim3(64 * NW), 0, s, A);
-          return hipGetLastError();
-        }
-      });
-    });
-  });
-}
-
-hipError_t launch_batch(const BatchArgs& B, int dtype, const MacShape& shape, int grid, const float* in,
-                        int64_t in_stride, float* hist, float* ola, float* out, int64_t out_stride, hipStream_t s,
-                        hipEvent_t* ev) {
-  if (B.n_blocks <= 0) return hipSuccess;
-  return by_hop(B.P.L, [&](auto Lc) {
-    return by_dtype(dtype, [&](auto Dc) {
-      constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value;
-      using ST = typename Store<DT>::T;
-      hipError_t e = hipSuccess;
-      if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_batch_spectra<L, DT>), dim3(B.n_blocks, B.P.I), dim3(256), 0, s, B.P, in, in_stride,
-                         hist, static_cast<ST*>(B.fdl), B.counter);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-      if (B.n_mac > 0) {
-        e = by_shape(shape, [&](auto Vc, auto Gc, auto NWc) {
-          constexpr int V = decltype(Vc)::value, G = decltype(Gc)::value, NW = decltype(NWc)::value;
-          if constexpr (64 * V > 2 * L) {
-            return hipErrorInvalidValue;
-          } else {
-            hipLaunchKernelGGL((k_batch_mac<L, V, G, NW, DT>), dim3(grid), dim3(64 * NW), 0, s, B);
-            return hipGetLastError();
-          }
-        });
-        if (e != hipSuccess) return e;
-      }
-      if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-      const int wgs = B.P.C > B.P.I ? B.P.C : B.P.I;
-      hipLaunchKernelGGL((k_batch_ola<L>), dim3(wgs), dim3(256), 0, s, B, in, in_stride, hist, B.ola_state, out,
-                         out_stride);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      if (ev) e = hipEventRecord(ev[3], s);
-      return e;
-    });
-  });
-}
-
-hipError_t launch_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M, void* dst,
-                         hipStream_t s) {
-  return by_hop(P.L, [&](auto Lc) {
-    return by_dtype(dtype, [&](auto Dc) {
-      constexpr int L = decltype(Lc)::value, DT = decltype(Dc)::value;
-      hipLaunchKernelGGL((k_irprep<L, DT>), dim3(M), dim3(64), 0, s, P, taps, n_taps,
-                         static_cast<typename Store<DT>::T*>(dst));
-      return hipGetLastError();
-    });
-  });
-}
-
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes == 0) return hipSuccess;
   const size_t n16 = bytes / 16;
@@ -930,5 +1245,6 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
                      static_cast<uint8_t*>(p) + n16 * 16, ntail);
   return hipGetLastError();
 }
+#endif
 
 }  // namespace tvx
