@@ -7,13 +7,15 @@ transform-out and overlap-add, for all channels, with the IR slot of every
 channel switching every block. Inputs, IR bank, schedule and outputs are
 resident in HBM before timing starts.
 
-By default blocks go through the library 16 at a time (tvolap_process_blocks,
-output identical to one call per block); the same run also times strict
-streaming with one call per block (realtime_one_block_per_call).
+By default blocks go through the library 64 at a time (tvolap_process_blocks:
+the same output as one call per block up to the order of additions), and the
+calls of a step are replayed from one captured HIP graph; the same run also
+times strict streaming with one call per block (realtime_one_block_per_call).
 
-Prints one JSON line with the roofline of the dominant kernel (HIP events
-recorded by the library around its launches over the timed region) and a CPU
-baseline (the FP64 oracle on a bounded sample of the same workload).
+Prints one JSON line with the roofline of the dominant kernel (its average
+launch duration from HIP events that the library records around it on its
+stream), an accuracy check of the same configuration against the FP64 oracle,
+and a CPU baseline (the oracle on a bounded sample of the same workload).
 """
 from __future__ import annotations
 
@@ -86,15 +88,11 @@ def measured_traffic(case: str):
     return None
 
 
-TIME_BLOCK = 8   # blocks of one parity per time-blocked MAC item (batched calls)
-
-
 def tmac_unique_bytes(wl, batch: int, store_bytes: int) -> int:
-    """Bytes that the time-blocked MAC of batched calls must read at least over
-    one pass of the workload: per time group (up to TIME_BLOCK blocks of one
-    parity in one call), every delay-line spectrum the group touches once per
-    input (M_i + blocks - 1 rows) and every partition spectrum once per
-    distinct slot per channel."""
+    """Bytes that the spectral MAC of batched calls must read at least over one
+    pass of the workload: per call, every partition spectrum of every slot a
+    channel uses in the call once, and per input and parity class the
+    delay-line spectra its blocks reach once (M_i + blocks - 1 rows)."""
     L = wl.hop
     row = 2 * L * store_bytes
     Mc = np.array([-(-int(t) // (2 * L)) for t in wl.taps_of_channel], dtype=np.int64)
@@ -106,14 +104,12 @@ def tmac_unique_bytes(wl, batch: int, store_bytes: int) -> int:
     for c0 in range(0, wl.n_calls, batch):
         n = min(batch, wl.n_calls - c0)
         for cls in (0, 1):
-            js = list(range(cls, n, 2))
-            for g0 in range(0, len(js), TIME_BLOCK):
-                grp = [c0 + j for j in js[g0:g0 + TIME_BLOCK]]
-                nb = len(grp)
+            nb = len(range(cls, n, 2))
+            if nb:
                 total += int((Mi + nb - 1).sum()) * row
-                slots = np.clip(wl.schedule[grp], 0, wl.n_slots - 1)           # [nb][C]
-                distinct = np.array([len(np.unique(slots[:, c])) for c in range(wl.n_channels)])
-                total += int((distinct * Mc).sum()) * row
+        slots = np.clip(wl.schedule[c0:c0 + n], 0, wl.n_slots - 1)           # [n][C]
+        distinct = np.array([len(np.unique(slots[:, c])) for c in range(wl.n_channels)])
+        total += int((distinct * Mc).sum()) * row
     return total
 
 
@@ -169,12 +165,15 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
-    ap.add_argument("--batch", type=int, default=16,
+    ap.add_argument("--batch", type=int, default=64,
                     help="blocks per call (1 = strict streaming, one block per call; >1 = batched calls)")
+    ap.add_argument("--bchunk", type=int, default=0, help="batched MAC: partitions per work item")
+    ap.add_argument("--bvec", type=int, default=0, help="batched MAC: complex bins per lane (1 or 2)")
+    ap.add_argument("--bwaves", type=int, default=0, help="batched MAC: waves per workgroup (1, 2 or 4)")
     ap.add_argument("--no-realtime", action="store_true",
                     help="skip the extra one-block-per-call measurement")
-    ap.add_argument("--graph", action="store_true",
-                    help="capture one step (all blocks) in a HIP graph and replay it per step")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="issue the calls of a step directly instead of replaying one captured HIP graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB float32 buffer 5 times (hardware-counter calibration)")
     args = ap.parse_args()
@@ -279,7 +278,9 @@ def run(args, spec, wl, stream):
     t_setir = time.perf_counter() - t0
     tuned_us = None
     tuned_batch_us = None
-    if args.batch > 1 and not args.no_autotune:
+    if args.batch > 1 and (args.bchunk or args.bvec or args.bwaves):
+        conv.configure_batch(chunk=args.bchunk, vec=args.bvec, waves=args.bwaves)
+    elif args.batch > 1 and not args.no_autotune:
         t0 = time.perf_counter()
         tuned_batch_us = conv.autotune_batch(iters=3)
         log(f"batched schedule autotuned in {time.perf_counter() - t0:.2f} s: best {tuned_batch_us:.2f} us/block")
@@ -319,6 +320,7 @@ def run(args, spec, wl, stream):
         log(f"warmup {w + 1}/{args.warmup} done")
 
     per_kernel = not args.no_kernel_timing and not args.graph and (args.mode != "fused" or args.batch > 1)
+    kernel_pass = not args.no_kernel_timing and args.graph and args.batch > 1
     if per_kernel:
         conv.set_timing(True)
         conv.get_timing()
@@ -336,8 +338,20 @@ def run(args, spec, wl, stream):
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
     timing = conv.get_timing() if per_kernel else None
     conv.set_timing(False)
+    if kernel_pass:
+        # kernel durations do not depend on how the launches were issued: time
+        # the same calls once more without the graph, with the library's events
+        conv.set_timing(True)
+        conv.get_timing()
+        for k in range(max(1, args.steps // 2)):
+            conv.process(x, sched, out, batch=args.batch)
+        timing = conv.get_timing()
+        conv.set_timing(False)
+        timing_steps = max(1, args.steps // 2)
+    else:
+        timing_steps = args.steps
     calls_per_step = -(-wl.n_calls // args.batch)
-    if not per_kernel and not args.no_kernel_timing:
+    if not per_kernel and not kernel_pass and not args.no_kernel_timing:
         # One kernel per block: the events that bracket the timed region on the
         # convolver's stream give its average launch duration (inter-launch
         # gaps included, so this is an upper bound on the kernel's time).
@@ -347,7 +361,7 @@ def run(args, spec, wl, stream):
             timing = None
 
     realtime = None
-    if args.batch > 1 and not args.no_realtime and not args.graph:
+    if args.batch > 1 and not args.no_realtime:
         # strict streaming: one block per call, same workload
         conv.process(x, sched, out, batch=1)
         torch.cuda.synchronize()
@@ -371,7 +385,7 @@ def run(args, spec, wl, stream):
     roof = None
     if timing and timing["blocks"] > 0 and args.batch > 1:
         # dominant kernel: k_tmac, one launch per call over its blocks
-        launches = args.steps * calls_per_step
+        launches = timing_steps * calls_per_step
         mac_ms = timing["ms_mac"] / launches
         store = 8 if spec["dtype"] == "f32" else 4
         kbytes = tmac_unique_bytes(wl, args.batch, store) / calls_per_step
@@ -384,7 +398,7 @@ def run(args, spec, wl, stream):
                 "traffic_source": tr[1] if tr else None,
                 "kernel": "k_tmac (time-blocked spectral MAC of eq. 8 over a batch of blocks)",
                 "bytes_per_launch": int(kbytes), "avg_launch_us": round(mac_ms * 1e3, 3),
-                "bytes_note": "unique delay-line and partition spectra of each time group",
+                "bytes_note": "unique delay-line and partition spectra of each call",
                 "per_block_bytes_per_launch": int(per_block),
                 "effective_gbs_per_block_bytes": round(per_block / (mac_ms * 1e-3) / 1e9, 1),
                 "phase_us_per_block": {"in": round(1e3 * timing["ms_in"] / timing["blocks"], 3),

@@ -854,10 +854,11 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   B.ypart = h->d_bypart;
   B.yblk = h->d_yblk;
   B.ola_state = h->d_ola;
+  B.arrive = h->d_arrive;
   B.done = h->d_done;
   B.counter = h->d_counter;
   const int groups = ((n_blocks + 1) / 2 + tvx::kTimeBlock - 1) / tvx::kTimeBlock;
-  const int grid = h->n_bmac * 2 * groups;
+  const int grid = 8 * ((2 * h->n_bmac + 7) / 8) * groups;   // k_tmac's XCD-aware index space
   TimingSet* ts = nullptr;
   if (h->timing && !h->capturing) {
     ts = &h->tsets[h->tnext];

@@ -103,6 +103,7 @@ struct BatchArgs {
   float2* ypart;               // [n_max][rows][tile_width]
   float* yblk;                 // [n_max][C][4L]
   float* ola_state;            // [C][3L]
+  int32_t* arrive;             // [C] overlap-add workgroups finished per channel (zero between calls)
   int32_t* done;
   uint64_t* counter;
 };

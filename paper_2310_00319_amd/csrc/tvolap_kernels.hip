@@ -589,20 +589,29 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
   using ST = typename Store<DT>::T;
   constexpr int N = 2 * L;
   const int TW = B.tile_width;   // 64 V bins per wave, blockDim.x / 64 waves
-  constexpr int PD = 2;   // partitions loaded ahead
+  constexpr int PD = 4;   // partitions loaded ahead
   const DevPlan& P = B.P;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const uint64_t cnt0 = *B.counter;
   const int n = B.n_blocks;
   const int groups = ((n + 1) / 2 + TB - 1) / TB;     // time groups per parity class
-  const int total = B.n_mac * 2 * groups;
+  // Workgroup w runs on XCD w mod 8. The time groups of one (item, parity
+  // class) read the same partition spectra, so they get indices 8 apart: the
+  // same XCD (and L2), dispatched one after the other.
+  const int pairs = 2 * B.n_mac;                      // (item, class)
+  const int lanes8 = (pairs + 7) / 8;
+  const int total = 8 * lanes8 * groups;
   const ST* bank = static_cast<const ST*>(B.bank);
   const ST* fdl = static_cast<const ST*>(B.fdl);
   for (int idx = blockIdx.x; idx < total; idx += gridDim.x) {
-    const int tg = idx / B.n_mac;
-    const WorkItem it = B.items[idx - tg * B.n_mac];
-    const int j0 = (tg & 1) + 2 * TB * (tg >> 1);       // first block of the group
+    const int x = idx & 7, y = idx >> 3;
+    const int gi = y % groups;
+    const int pr = x + 8 * (y / groups);               // (item, class) pair
+    if (pr >= pairs) continue;
+    const int cls = pr & 1;
+    const WorkItem it = B.items[pr >> 1];
+    const int j0 = cls + 2 * TB * gi;                  // first block of the group
     if (j0 >= n) continue;
     const int nb = min(TB, (n - j0 + 1) / 2);            // blocks j0, j0 + 2, ...
     const int i = uniform(it.input);
@@ -880,78 +889,98 @@ __global__ __launch_bounds__(256) void k_batch_inv(BatchArgs B) {
   inverse_store<L, T>(Y, bufA, bufB, twl, B.yblk + ((int64_t)j * P.C + c) * 4 * L, tid);
 }
 
-// One workgroup per channel (and per input for the history): overlap-add of
-// the batch's n blocks (eq. 10-13 in the two-step form). Emitted window j of
-// the batch (samples jL .. jL+L) is the carried state for j < 3 plus the
-// quarter d of block j - d for d = 0..3; the new carried state (3L samples)
-// is what reaches past the last window. Every block sample is read once, and
-// all windows are independent, so the whole batch is one parallel pass; the
-// old state is staged in LDS so that it can be overwritten in place. The
-// workgroups advance the call count by n once every one of them has read it.
+// Overlap-add of the batch's n blocks (eq. 10-13 in the two-step form), grid
+// (max(C, I), S): workgroup (c, s) emits a range of 4 x 256 samples of
+// channel c. Emitted window j of the batch (samples jL .. jL+L) is the carried
+// state for j < 3 plus the quarter d of block j - d for d = 0..3, summed
+// oldest block first (the order of one-block calls); every block sample is
+// read once. The carried state (3L samples) is replaced by the last workgroup
+// of the channel to finish: every workgroup reads the old state it needs
+// before it arrives, so nothing waits and the old state is never overwritten
+// early. Workgroups with s = 0 also store the input history (rows c < I) and
+// the selection; the last workgroup of the grid advances the call count by n.
 template <int L>
 __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __restrict__ in, int64_t in_stride,
                                                    float* __restrict__ hist, float* __restrict__ ola,
                                                    float* __restrict__ out, int64_t out_stride) {
   constexpr int T = 256;
+  constexpr int R = 4;                     // samples per thread
+  constexpr int SPW = R * T;               // samples per workgroup
   const DevPlan& P = B.P;
-  const int c = blockIdx.x, tid = threadIdx.x;
+  const int c = blockIdx.x, sw = blockIdx.y, tid = threadIdx.x;
   const int n = B.n_blocks;
   const uint64_t cnt0 = *B.counter;
+  __shared__ int last;
   if (c < P.C) {
-    __shared__ float st_old[3 * L];
     float* st = ola + (int64_t)c * 3 * L;
-    for (int u = tid; u < 3 * L; u += T) st_old[u] = st[u];
-    __syncthreads();
     const float* yc = B.yblk + (int64_t)c * 4 * L;     // block j at yc + j * C * 4L
     const int64_t ystride = (int64_t)P.C * 4 * L;
     float* oc = out + (int64_t)c * out_stride;
-    // emitted samples t = jL + k, j < n; eight per thread at a time, all
-    // loads issued before the stores
-    constexpr int R = 8;
-    for (int t0 = 0; t0 < n * L; t0 += R * T) {
-      float v[R];
+    const int t0 = sw * SPW;
+    float v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int t = t0 + r * T + tid;
-        v[r] = 0.f;
-        if (t < n * L) {
-          const int j = t / L, k = t - j * L;
-          float a = (j < 3) ? st_old[j * L + k] : 0.f;
-          // oldest block first: the order in which one-block calls accumulate
+    for (int r = 0; r < R; ++r) {
+      const int t = t0 + r * T + tid;
+      v[r] = 0.f;
+      if (t < n * L) {
+        const int j = t / L, k = t - j * L;
+        float a = (j < 3) ? st[j * L + k] : 0.f;
 #pragma unroll
-          for (int d = 3; d >= 0; --d)
-            if (j - d >= 0) a += yc[(int64_t)(j - d) * ystride + d * L + k];
-          v[r] = a;
+        for (int d = 3; d >= 0; --d)
+          if (j - d >= 0) a += yc[(int64_t)(j - d) * ystride + d * L + k];
+        v[r] = a;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int t = t0 + r * T + tid;
+      if (t < n * L) oc[t] = v[r];
+    }
+    // every read of the old state above has returned (its value is stored)
+    __syncthreads();
+    if (tid == 0) last = (atomicAdd(&B.arrive[c], 1) == (int)gridDim.y - 1) ? 1 : 0;
+    __syncthreads();
+    if (last) {
+      // new carried state u = qL + k: windows n + q, q < 3; all of it is read
+      // before any of it is written
+      constexpr int NS = (3 * L + T - 1) / T;
+      float ns[NS];
+#pragma unroll
+      for (int e = 0; e < NS; ++e) {
+        const int u = tid + e * T;
+        ns[e] = 0.f;
+        if (u < 3 * L) {
+          const int q = u / L, k = u - q * L;
+          float a = (n + q < 3) ? st[(n + q) * L + k] : 0.f;
+#pragma unroll
+          for (int d = 3; d >= 1; --d) {
+            const int j = n + q - d;
+            if (d > q && j >= 0) a += yc[(int64_t)j * ystride + d * L + k];
+          }
+          ns[e] = a;
         }
       }
+      __syncthreads();
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int t = t0 + r * T + tid;
-        if (t < n * L) oc[t] = v[r];
+      for (int e = 0; e < NS; ++e) {
+        const int u = tid + e * T;
+        if (u < 3 * L) st[u] = ns[e];
+      }
+      if (tid == 0) {
+        B.arrive[c] = 0;
+        if (B.copy_sel) B.sel_store[c] = B.sel[(int64_t)(n - 1) * B.sel_stride + c];
       }
     }
-    // new carried state u = qL + k: windows n + q, q < 3
-    for (int u = tid; u < 3 * L; u += T) {
-      const int q = u / L, k = u - q * L;
-      float v = (n + q < 3) ? st_old[(n + q) * L + k] : 0.f;
-#pragma unroll
-      for (int d = 3; d >= 1; --d) {
-        const int j = n + q - d;
-        if (d > q && j >= 0) v += yc[(int64_t)j * ystride + d * L + k];
-      }
-      st[u] = v;
-    }
-    if (tid == 0 && B.copy_sel) B.sel_store[c] = B.sel[(int64_t)(n - 1) * B.sel_stride + c];
   }
-  if (c < P.I) {
-    const uint64_t last = cnt0 + (uint64_t)(n - 1);
-    float* hnew = hist + ((size_t)(last & 1u) * P.I + c) * L;
+  if (c < P.I && sw == 0) {
+    const uint64_t lastc = cnt0 + (uint64_t)(n - 1);
+    float* hnew = hist + ((size_t)(lastc & 1u) * P.I + c) * L;
     const float* xin = in + (int64_t)c * in_stride + (int64_t)(n - 1) * L;
     for (int k = tid; k < L; k += T) hnew[k] = xin[k];
   }
   __syncthreads();
   if (tid == 0) {
-    if (atomicAdd(B.done, 1) == (int)gridDim.x - 1) {
+    if (atomicAdd(B.done, 1) == (int)(gridDim.x * gridDim.y) - 1) {
       *B.done = 0;
       *B.counter = cnt0 + (uint64_t)n;
     }
@@ -1188,7 +1217,8 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int wgs = B.P.C > B.P.I ? B.P.C : B.P.I;
-    hipLaunchKernelGGL((k_batch_ola<L>), dim3(wgs), dim3(256), 0, s, B, in, in_stride, hist, B.ola_state, out,
+    const int spw = (B.n_blocks * L + 4 * 256 - 1) / (4 * 256);   // 4 samples per thread, 256 threads
+    hipLaunchKernelGGL((k_batch_ola<L>), dim3(wgs, spw), dim3(256), 0, s, B, in, in_stride, hist, B.ola_state, out,
                        out_stride);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
