@@ -33,6 +33,10 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# FP32 fused multiply-add issue rate without packed-FP32 instructions (which
+# this build does not emit): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+# With packed FP32 the chip's published vector figure is twice this, 157.3.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 WORKLOADS = {
     "binaural": dict(desc="64 sources x 2 ears = 128 channels, L=256 (blocks 512, FFT 1024), 96000-tap IRs "
@@ -170,6 +174,7 @@ def main():
     ap.add_argument("--bchunk", type=int, default=0, help="batched MAC: partitions per work item")
     ap.add_argument("--bvec", type=int, default=0, help="batched MAC: complex bins per lane (1 or 2)")
     ap.add_argument("--bwaves", type=int, default=0, help="batched MAC: waves per workgroup (1, 2 or 4)")
+    ap.add_argument("--btb", type=int, default=0, help="batched MAC: blocks per time group (8 or 16)")
     ap.add_argument("--no-realtime", action="store_true",
                     help="skip the extra one-block-per-call measurement")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
@@ -278,8 +283,8 @@ def run(args, spec, wl, stream):
     t_setir = time.perf_counter() - t0
     tuned_us = None
     tuned_batch_us = None
-    if args.batch > 1 and (args.bchunk or args.bvec or args.bwaves):
-        conv.configure_batch(chunk=args.bchunk, vec=args.bvec, waves=args.bwaves)
+    if args.batch > 1 and (args.bchunk or args.bvec or args.bwaves or args.btb):
+        conv.configure_batch(chunk=args.bchunk, vec=args.bvec, waves=args.bwaves, time_block=args.btb)
     elif args.batch > 1 and not args.no_autotune:
         t0 = time.perf_counter()
         tuned_batch_us = conv.autotune_batch(iters=3)
@@ -384,20 +389,35 @@ def run(args, spec, wl, stream):
 
     roof = None
     if timing and timing["blocks"] > 0 and args.batch > 1:
-        # dominant kernel: k_tmac, one launch per call over its blocks
+        # dominant kernel: k_tmac, one launch per call over its blocks. Two
+        # floors: the unique bytes it must read at 8 TB/s, and its complex
+        # multiply-adds (8 flop each) at the FP32 FMA issue rate; the larger one
+        # is the bound the kernel is measured against.
         launches = timing_steps * calls_per_step
         mac_ms = timing["ms_mac"] / launches
         store = 8 if spec["dtype"] == "f32" else 4
         kbytes = tmac_unique_bytes(wl, args.batch, store) / calls_per_step
-        achieved = kbytes / (mac_ms * 1e-3) / 1e9
+        kflops = 8.0 * info["sum_partitions"] * 2 * wl.hop * wl.n_calls / calls_per_step
+        gbs = kbytes / (mac_ms * 1e-3) / 1e9
+        tfs = kflops / (mac_ms * 1e-3) / 1e12
+        floor_hbm = kbytes / (HBM_PEAK_GBS * 1e9)
+        floor_alu = kflops / (VALU_PEAK_TFLOPS * 1e12)
         per_block = info["mac_bytes_per_block"] * wl.n_calls / calls_per_step
         tr = measured_traffic(f"{args.workload} batch{args.batch} k_tmac")
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr[0] if tr else None,
+        hbm = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+               "bytes_per_launch": int(kbytes), "floor_us": round(floor_hbm * 1e6, 2)}
+        alu = {"achieved": round(tfs, 2), "peak": round(VALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
+               "frac": round(tfs / VALU_PEAK_TFLOPS, 4), "flops_per_launch": int(kflops),
+               "floor_us": round(floor_alu * 1e6, 2),
+               "peak_note": "FP32 FMA issue rate without packed-FP32 instructions (256 CU x 4 SIMD x 16 lanes x "
+                            "2 flop x 2.4 GHz); the published packed figure is 157.3"}
+        main, other = (("hbm", hbm), ("alu", alu)) if floor_hbm >= floor_alu else (("alu", alu), ("hbm", hbm))
+        roof = {"bound": main[0], "achieved": main[1]["achieved"], "peak": main[1]["peak"], "unit": main[1]["unit"],
+                "frac": main[1]["frac"], "traffic": tr[0] if tr else None,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "traffic_source": tr[1] if tr else None,
                 "kernel": "k_tmac (time-blocked spectral MAC of eq. 8 over a batch of blocks)",
-                "bytes_per_launch": int(kbytes), "avg_launch_us": round(mac_ms * 1e3, 3),
+                "avg_launch_us": round(mac_ms * 1e3, 3), main[0]: main[1], other[0]: other[1],
                 "bytes_note": "unique delay-line and partition spectra of each call",
                 "per_block_bytes_per_launch": int(per_block),
                 "effective_gbs_per_block_bytes": round(per_block / (mac_ms * 1e-3) / 1e9, 1),
@@ -476,6 +496,7 @@ def run(args, spec, wl, stream):
                      "waves": info["mac_waves"], "grid": info["mac_grid"], "work_items": info["n_work_items"],
                      "autotuned_us_per_block": tuned_us,
                      "batch": {"chunk": info["batch_chunk"], "vec": info["batch_vec"], "waves": info["batch_waves"],
+                               "time_block": info["batch_time_block"],
                                "tile_width": info["batch_tile_width"], "work_items": info["batch_work_items"],
                                "autotuned_us_per_block": tuned_batch_us}},
     }

@@ -93,9 +93,10 @@ typedef struct {
   int32_t batch_vec;                /* complex bins per lane                             */
   int32_t batch_waves;              /* waves per workgroup (each owns 64 vec bins)       */
   int32_t batch_tile_width;         /* bins per work item: 64 vec waves                  */
-  int32_t batch_work_items;         /* items per time group (parity class of up to 8
-                                       blocks of a batch)                                */
+  int32_t batch_work_items;         /* items per time group (a parity class of up to
+                                       batch_time_block blocks of a call)                */
   int32_t batch_rows;               /* partial-spectrum rows per block                   */
+  int32_t batch_time_block;         /* blocks of one parity per time group (8 or 16)     */
 } tvolap_info;
 
 /* Create a convolver (Sec. 2: partitioned, block-synchronously switchable,
@@ -198,20 +199,21 @@ int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, i
 int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us);
 
 /* Schedule of batched calls (tvolap_process_blocks; no effect on results
- * beyond the order of floating-point additions). The spectral MAC of a batch
- * works on time groups: up to 8 blocks of the same parity, which read
+ * beyond the order of floating-point additions). The spectral MAC of a call
+ * works on time groups: up to time_block blocks of the same parity, which read
  * overlapping delay-line spectra (block l + 2 at partition m + 1 reads what
  * block l reads at partition m, eq. 8) and, where their slots agree, the same
  * partition spectra. chunk: partitions per work item (0 = about one workgroup
- * per compute unit); vec: complex bins per lane (1 or 2; 0 = 2); waves: 1, 2 or 4 waves per workgroup,
- * each owning 64 vec bins (0 = 4, fewer when 2L bins are fewer). Waits for
- * the stream; rebuilds the batched work list. Errors: EINVAL, ESTATE during
- * capture, ENOMEM/EDEVICE. */
-int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves);
+ * per compute unit); vec: complex bins per lane (1 or 2; 0 = 2, or 1 with time
+ * groups of 16); waves: 1, 2 or 4 waves per workgroup, each owning 64 vec bins
+ * (0 = 4, fewer when 2L bins are fewer); time_block: 8 or 16 (16 needs vec 1;
+ * 0 = 16 when max_batch >= 32, else 8). Waits for the stream; rebuilds the
+ * batched work list. Errors: EINVAL, ESTATE during capture, ENOMEM/EDEVICE. */
+int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block);
 
 /* Autotuner for batched calls: times `iters` calls of max_batch blocks (zero
  * input, current bank, block b of the batch in slot b mod K) for each
- * candidate (vec, waves, chunk), keeps the fastest, caches it for handles of
+ * candidate (time_block, vec, waves, chunk), keeps the fastest, caches it for handles of
  * the same shape and max_batch in this process, then resets the stream state
  * as tvolap_reset does. *best_us (may be NULL) receives the best time per
  * block in microseconds, or -1 when the choice came from the cache.

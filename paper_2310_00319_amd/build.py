@@ -1,8 +1,8 @@
 """Build libtvolap.so for gfx950 in-tree with hipcc.
 
-The kernel file is compiled once per supported hop (64, 128, 256, 512); all
-translation units compile in parallel and are then linked into one shared
-library.
+The kernel file is compiled once per supported hop (64, 128, 256, 512) and
+spectra storage type (f32, bf16, f16); all translation units compile in
+parallel and are then linked into one shared library.
 
 Usage: python -m paper_2310_00319_amd.build   (or call build()).
 """
@@ -20,7 +20,9 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtvolap.so")
 HOPS = (64, 128, 256, 512)
 # (source, extra flags, object name)
-UNITS = [("tvolap_kernels.hip", [f"-DTVX_HOP={L}"], f"tvolap_kernels_L{L}.o") for L in HOPS] + [
+DTYPES = (0, 1, 2)   # f32, bf16, f16 storage
+UNITS = [("tvolap_kernels.hip", [f"-DTVX_HOP={L}", f"-DTVX_DT={d}"], f"tvolap_kernels_L{L}_d{d}.o")
+         for L in HOPS for d in DTYPES] + [
     ("tvolap_offline.hip", [], "tvolap_offline.o"),
     ("tvolap_dispatch.cpp", [], "tvolap_dispatch.o"),
     ("tvolap_capi.cpp", [], "tvolap_capi.o"),

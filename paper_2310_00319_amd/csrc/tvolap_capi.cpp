@@ -47,7 +47,7 @@ struct MacChoice {
 // (0 = automatic), complex bins per lane (0 = automatic), waves per tile
 // (0 = automatic).
 struct BatchChoice {
-  int32_t chunk = 0, vec = 0, waves = 0;
+  int32_t chunk = 0, vec = 0, waves = 0, time_block = 0;
 };
 
 // Autotuner results, keyed by the handle's shape (hop, channels, inputs,
@@ -113,7 +113,7 @@ struct tvolap {
   // batched blocks: time-blocked MAC work list (partitions from 0)
   MacShape bshape{2, 1, 4};
   BatchChoice bchoice;
-  int32_t b_tile_width = 512, b_chunk = 0, n_bmac = 0, n_brows = 0;
+  int32_t b_tile_width = 512, b_chunk = 0, n_bmac = 0, n_brows = 0, b_tb = 8;
   std::vector<WorkItem> bitems;
   std::vector<int32_t> b_row_base, b_nchunks;
   WorkItem* d_bitems = nullptr;
@@ -336,10 +336,15 @@ void build_work(tvolap_t* h, int S_req, int waves, int vec) {
 // input (up to 2 per item), the 2L bins cut into tiles of 64 V NW, each
 // group's partitions [0, M) cut into chunks of S. The partial rows of a
 // channel are contiguous in (tile, chunk) order. Each item runs once per
-// time group (a parity class of up to kTimeBlock blocks of the batch).
+// time group (a parity class of up to b_tb (8 or 16) blocks of the call).
 void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   const int N = 2 * h->L;
+  // time groups of 16 blocks (one bin per lane) when calls can hold 32 blocks
   int V = (bc.vec == 1) ? 1 : 2;
+  int TB = bc.time_block == 16 ? 16 : (bc.time_block == 8 ? 8 : (h->max_batch >= 32 ? 16 : 8));
+  if (TB == 16 && bc.vec == 0) V = 1;
+  if (TB == 16 && V != 1) TB = 8;
+  h->b_tb = TB;
   while (64 * V > N && V > 1) V /= 2;
   int NW = bc.waves > 0 ? bc.waves : 4;
   NW = NW >= 4 ? 4 : (NW >= 2 ? 2 : 1);
@@ -453,6 +458,7 @@ int apply_batch_choice(tvolap_t* h, const BatchChoice& c) {
   h->bchoice.chunk = h->b_chunk;
   h->bchoice.vec = h->bshape.V;
   h->bchoice.waves = h->bshape.NW;
+  h->bchoice.time_block = h->b_tb;
   return TVOLAP_OK;
 }
 
@@ -843,6 +849,7 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   B.n_blocks = n_blocks;
   B.n_rows = h->n_brows;
   B.tile_width = h->b_tile_width;
+  B.time_block = h->b_tb;
   B.row_base = h->d_brow_base;
   B.nchunks = h->d_bnchunks;
   B.bank = h->d_bank;
@@ -857,7 +864,7 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   B.arrive = h->d_arrive;
   B.done = h->d_done;
   B.counter = h->d_counter;
-  const int groups = ((n_blocks + 1) / 2 + tvx::kTimeBlock - 1) / tvx::kTimeBlock;
+  const int groups = ((n_blocks + 1) / 2 + h->b_tb - 1) / h->b_tb;
   const int grid = 8 * ((2 * h->n_bmac + 7) / 8) * groups;   // k_tmac's XCD-aware index space
   TimingSet* ts = nullptr;
   if (h->timing && !h->capturing) {
@@ -892,16 +899,20 @@ int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, i
   return apply_choice(h, c);
 }
 
-int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves) {
+int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block) {
   if (!h) return TVOLAP_EINVAL;
   if (h->capturing) return fail(h, TVOLAP_ESTATE, "cannot reconfigure during graph capture");
   if (chunk < 0) return fail(h, TVOLAP_EINVAL, "chunk must be >= 0");
   if (vec != 0 && vec != 1 && vec != 2) return fail(h, TVOLAP_EINVAL, "vec must be 0, 1 or 2");
   if (waves != 0 && waves != 1 && waves != 2 && waves != 4) return fail(h, TVOLAP_EINVAL, "waves must be 0, 1, 2 or 4");
+  if (time_block != 0 && time_block != 8 && time_block != 16)
+    return fail(h, TVOLAP_EINVAL, "time_block must be 0, 8 or 16");
+  if (time_block == 16 && vec == 2) return fail(h, TVOLAP_EINVAL, "time_block 16 needs vec 1");
   BatchChoice c;
   c.chunk = chunk;
   c.vec = vec;
   c.waves = waves;
+  c.time_block = time_block;
   return apply_batch_choice(h, c);
 }
 
@@ -928,7 +939,8 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
     for (int c = 0; c < h->C; ++c) maxM[h->ch_input[c]] = std::max(maxM[h->ch_input[c]], h->ch_M[c]);
     for (int i = 0; i < h->I; ++i) units += maxM[i];
   }
-  const int tgroups = 2 * (((nb + 1) / 2 + tvx::kTimeBlock - 1) / tvx::kTimeBlock);
+  std::vector<int> tbs = {8};
+  if (nb >= 32) tbs.push_back(16);
   // zero input and scratch output of one full batch, for the timing only
   float* tin = nullptr;
   float* tout = nullptr;
@@ -952,7 +964,10 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
   float best_t = 1e30f;
   int rc = TVOLAP_OK;
   const std::vector<int> vecs = {1, 2};
+  for (int tb : tbs)
   for (int vec : vecs) {
+    if (tb == 16 && vec != 1) continue;
+    const int tgroups = 2 * (((nb + 1) / 2 + tb - 1) / tb);
     for (int nw : {1, 2, 4}) {
       if (64 * vec * nw > N) continue;
       const int tiles = N / (64 * vec * nw);
@@ -968,6 +983,7 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
         c.chunk = S;
         c.vec = vec;
         c.waves = nw;
+        c.time_block = tb;
         rc = apply_batch_choice(h, c);
         if (rc != TVOLAP_OK) break;
         // every block of the batch selects slot (block mod K), as a switching stream does
@@ -1178,6 +1194,7 @@ int tvolap_get_info(const tvolap_t* h, tvolap_info* info) {
   info->batch_tile_width = h->b_tile_width;
   info->batch_work_items = h->n_bmac;
   info->batch_rows = h->n_brows;
+  info->batch_time_block = h->b_tb;
   info->n_cu = h->n_cu;
   return TVOLAP_OK;
 }

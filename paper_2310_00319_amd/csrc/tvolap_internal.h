@@ -63,9 +63,6 @@ struct BlockArgs {
   int32_t inverse_inline;      // 1: last item of a channel transforms back; 0: a later kernel does
 };
 
-// Blocks of one parity per time-blocked MAC item in batched calls.
-constexpr int kTimeBlock = 8;
-
 struct MacShape {
   int32_t V;    // complex bins per lane (tile width = 64 V)
   int32_t G;    // channel capacity of a work item (1, 2 or 4)
@@ -92,6 +89,7 @@ struct BatchArgs {
   int32_t n_blocks;
   int32_t n_rows;              // partial rows of one block
   int32_t tile_width;          // bins per item tile (64 V NW)
+  int32_t time_block;          // blocks of one parity per MAC time group (8 or 16)
   const int32_t* row_base;     // [C] first partial row of channel c (rows ordered tile, chunk)
   const int32_t* nchunks;      // [C] partition chunks of channel c
   const void* bank;
@@ -116,23 +114,28 @@ hipError_t launch_irprep(const DevPlan& P, int dtype, const float* taps, int32_t
                          void* dst, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
-// The same launchers for one hop L, instantiated by the kernel file compiled
-// for that hop; launch_fwd and the others above pick one by P.L.
-template <int L>
+// The same launchers for one hop L and storage type DT, instantiated by the
+// kernel file compiled for that pair; launch_fwd and the others above pick one
+// by P.L and dtype.
+template <int L, int DT>
 hipError_t hop_fwd(const DevPlan& P, int dtype, const float* in, int64_t in_stride, float* hist, void* fdl,
                    const uint64_t* counter, hipStream_t s);
-template <int L>
+template <int L, int DT>
 hipError_t hop_inv(const DevPlan& P, int dtype, const float2* ypart, const void* bank, const void* fdl,
                    const int32_t* sel, float* ola, float* out, int64_t out_stride, int32_t copy_sel,
                    int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s);
-template <int L>
+template <int L, int DT>
 hipError_t hop_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s);
-template <int L>
+template <int L, int DT>
 hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int grid, const float* in,
                      int64_t in_stride, float* hist, float* ola, float* out, int64_t out_stride, hipStream_t s,
                      hipEvent_t* ev);
-template <int L>
+template <int L, int DT>
 hipError_t hop_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M, void* dst,
                       hipStream_t s);
+template <int DT>
+hipError_t mac_dt(const DevPlan& P, int dtype, const MacShape& shape, const WorkItem* items, int n_items,
+                  const void* bank, const void* fdl, const int32_t* sel, float2* ypart, const uint64_t* counter,
+                  hipStream_t s);
 
 }  // namespace tvx

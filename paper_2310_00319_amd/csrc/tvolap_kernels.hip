@@ -24,10 +24,11 @@
 #include "fft_lds.hpp"
 #include "tvolap_internal.h"
 
-#ifndef TVX_HOP
-#error "compile once per hop with -DTVX_HOP=64, 128, 256 or 512"
+#if !defined(TVX_HOP) || !defined(TVX_DT)
+#error "compile once per hop and storage type with -DTVX_HOP=64|128|256|512 -DTVX_DT=0|1|2"
 #endif
 static_assert(TVX_HOP == 64 || TVX_HOP == 128 || TVX_HOP == 256 || TVX_HOP == 512, "unsupported hop");
+static_assert(TVX_DT == 0 || TVX_DT == 1 || TVX_DT == 2, "unsupported storage type");
 
 namespace tvx {
 namespace {
@@ -662,8 +663,6 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[g][b][v] = make_float2(0.f, 0.f);
 
-    const bool dcw = (it.tile == 0 && w == 0);   // this wave holds the packed DC / Nyquist bin
-    const bool dc_lane = dcw && lane == 0;
     int mlast[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) mlast[g] = min(m1, McL[g]) - 1;
@@ -672,6 +671,8 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
     // delay-line rows of the current partition (block b at partition m0 + t
     // is in X[(b - t) mod TB]); Hq / Xq: ring of PD partitions' spectra and
     // next rows, loaded ahead of use.
+    const bool dcw = (it.tile == 0 && w == 0);   // this wave holds the packed DC / Nyquist bin
+    const bool dc_lane = dcw && lane == 0;
     auto run = [&](auto patc, auto dcwc, const ST* const (&hr)[G][2], const uint32_t (&sel1)[G],
                    const uint32_t (&take)[G]) {
       constexpr int PAT = decltype(patc)::value;
@@ -710,9 +711,9 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
             for (int d = 0; d < ND; ++d) {
 #pragma unroll
               for (int v = 0; v < V; ++v) {
-                const float2 h = Hs[g][d][v];
                 // complex product terms; on the DC lane (packed Re X(0),
                 // Re X(2L)) the product is component-wise
+                const float2 h = Hs[g][d][v];
                 float hx = h.x, hny = -h.y, hx2 = h.x, hy2 = h.y;
                 if (DCW && v == 0) {
                   hny = dc_lane ? 0.f : -h.y;
@@ -1088,14 +1089,11 @@ __global__ __launch_bounds__(256) void k_fill_zero(uint4* __restrict__ p, size_t
 
 // ---------------------------------------------------------------- dispatch
 
+// Storage types compiled in this file: TVX_DT only.
 template <typename F>
 hipError_t by_dtype(int dt, F&& f) {
-  switch (dt) {
-    case 0: return f(std::integral_constant<int, 0>{});
-    case 1: return f(std::integral_constant<int, 1>{});
-    case 2: return f(std::integral_constant<int, 2>{});
-    default: return hipErrorInvalidValue;
-  }
+  if (dt != TVX_DT) return hipErrorInvalidValue;
+  return f(std::integral_constant<int, TVX_DT>{});
 }
 
 template <typename F>
@@ -1142,11 +1140,11 @@ hipError_t by_bshape(const MacShape& sh, F&& f) {
 
 }  // namespace
 
-// Launchers that depend on the hop L. This file is compiled once per hop
-// (TVX_HOP) and instantiates them for that hop only; the hop-independent
-// launchers are compiled with the smallest hop.
+// Launchers that depend on the hop L. This file is compiled once per hop and
+// storage type (TVX_HOP, TVX_DT) and instantiates them for that pair only; the
+// hop-independent launchers are compiled with the smallest hop.
 
-template <int L>
+template <int L, int DTT>
 hipError_t hop_fwd(const DevPlan& P, int dtype, const float* in, int64_t in_stride, float* hist, void* fdl,
                    const uint64_t* counter, hipStream_t s) {
   return by_dtype(dtype, [&](auto Dc) {
@@ -1157,7 +1155,7 @@ hipError_t hop_fwd(const DevPlan& P, int dtype, const float* in, int64_t in_stri
   });
 }
 
-template <int L>
+template <int L, int DTT>
 hipError_t hop_inv(const DevPlan& P, int dtype, const float2* ypart, const void* bank, const void* fdl,
                    const int32_t* sel, float* ola, float* out, int64_t out_stride, int32_t copy_sel,
                    int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s) {
@@ -1170,7 +1168,7 @@ hipError_t hop_inv(const DevPlan& P, int dtype, const float2* ypart, const void*
   });
 }
 
-template <int L>
+template <int L, int DTT>
 hipError_t hop_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s) {
   if (A.n_items <= 0 || grid <= 0) return hipErrorInvalidValue;
   return by_dtype(dtype, [&](auto Dc) {
@@ -1187,7 +1185,7 @@ hipError_t hop_block(const BlockArgs& A, int dtype, const MacShape& shape, int g
   });
 }
 
-template <int L>
+template <int L, int DTT>
 hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int grid, const float* in,
                      int64_t in_stride, float* hist, float* ola, float* out, int64_t out_stride, hipStream_t s,
                      hipEvent_t* ev) {
@@ -1207,7 +1205,14 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
         constexpr int V = decltype(Vc)::value, G = decltype(Gc)::value;
         if (shape.NW != 1 && shape.NW != 2 && shape.NW != 4) return hipErrorInvalidValue;
         if (64 * V * shape.NW != B.tile_width || B.tile_width > 2 * L) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_tmac<L, V, G, kTimeBlock, DT>), dim3(grid), dim3(64 * shape.NW), 0, s, B);
+        if (B.time_block == 8) {
+          hipLaunchKernelGGL((k_tmac<L, V, G, 8, DT>), dim3(grid), dim3(64 * shape.NW), 0, s, B);
+        } else if constexpr (V == 1) {
+          if (B.time_block != 16) return hipErrorInvalidValue;
+          hipLaunchKernelGGL((k_tmac<L, V, G, 16, DT>), dim3(grid), dim3(64 * shape.NW), 0, s, B);
+        } else {
+          return hipErrorInvalidValue;
+        }
         return hipGetLastError();
       });
       if (e != hipSuccess) return e;
@@ -1227,7 +1232,7 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
   });
 }
 
-template <int L>
+template <int L, int DTT>
 hipError_t hop_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M, void* dst,
                       hipStream_t s) {
   return by_dtype(dtype, [&](auto Dc) {
@@ -1238,19 +1243,20 @@ hipError_t hop_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_
   });
 }
 
-template hipError_t hop_fwd<TVX_HOP>(const DevPlan&, int, const float*, int64_t, float*, void*, const uint64_t*,
+template hipError_t hop_fwd<TVX_HOP, TVX_DT>(const DevPlan&, int, const float*, int64_t, float*, void*, const uint64_t*,
                                      hipStream_t);
-template hipError_t hop_inv<TVX_HOP>(const DevPlan&, int, const float2*, const void*, const void*, const int32_t*,
+template hipError_t hop_inv<TVX_HOP, TVX_DT>(const DevPlan&, int, const float2*, const void*, const void*, const int32_t*,
                                      float*, float*, int64_t, int32_t, int32_t*, int32_t*, uint64_t*, hipStream_t);
-template hipError_t hop_block<TVX_HOP>(const BlockArgs&, int, const MacShape&, int, hipStream_t);
-template hipError_t hop_batch<TVX_HOP>(const BatchArgs&, int, const MacShape&, int, const float*, int64_t, float*,
+template hipError_t hop_block<TVX_HOP, TVX_DT>(const BlockArgs&, int, const MacShape&, int, hipStream_t);
+template hipError_t hop_batch<TVX_HOP, TVX_DT>(const BatchArgs&, int, const MacShape&, int, const float*, int64_t, float*,
                                        float*, float*, int64_t, hipStream_t, hipEvent_t*);
-template hipError_t hop_irprep<TVX_HOP>(const DevPlan&, int, const float*, int32_t, int32_t, void*, hipStream_t);
+template hipError_t hop_irprep<TVX_HOP, TVX_DT>(const DevPlan&, int, const float*, int32_t, int32_t, void*, hipStream_t);
 
 #if TVX_HOP == 64
-hipError_t launch_mac(const DevPlan& P, int dtype, const MacShape& shape, const WorkItem* items, int n_items,
-                      const void* bank, const void* fdl, const int32_t* sel, float2* ypart,
-                      const uint64_t* counter, hipStream_t s) {
+template <int DTT>
+hipError_t mac_dt(const DevPlan& P, int dtype, const MacShape& shape, const WorkItem* items, int n_items,
+                  const void* bank, const void* fdl, const int32_t* sel, float2* ypart, const uint64_t* counter,
+                  hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   return by_dtype(dtype, [&](auto Dc) {
     return by_shape(shape, [&](auto Vc, auto Gc, auto NWc) {
@@ -1264,6 +1270,11 @@ hipError_t launch_mac(const DevPlan& P, int dtype, const MacShape& shape, const 
   });
 }
 
+template hipError_t mac_dt<TVX_DT>(const DevPlan&, int, const MacShape&, const WorkItem*, int, const void*,
+                                   const void*, const int32_t*, float2*, const uint64_t*, hipStream_t);
+#endif
+
+#if TVX_HOP == 64 && TVX_DT == 0
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes == 0) return hipSuccess;
   const size_t n16 = bytes / 16;

@@ -51,12 +51,13 @@ MODES = {
 }
 
 
-def make_convolver(wl, dtype: str = "f32", stream=None, mode: str = "fused"):
+def make_convolver(wl, dtype: str = "f32", stream=None, mode: str = "fused", max_batch: int = 16):
     from paper_2310_00319_amd import Convolver
 
     conv = Convolver(hop=wl.hop, n_channels=wl.n_channels, max_taps=wl.max_taps(),
                      n_inputs=wl.n_inputs, input_of_channel=wl.input_of_channel,
-                     taps_of_channel=wl.taps_of_channel, n_slots=wl.n_slots, dtype=dtype, stream=stream)
+                     taps_of_channel=wl.taps_of_channel, n_slots=wl.n_slots, dtype=dtype, stream=stream,
+                     max_batch=max_batch)
     if mode != "fused":
         conv.configure(**MODES[mode])
     for c in range(wl.n_channels):
@@ -81,3 +82,31 @@ def gpu_streams(wl, dtype: str = "f32", conv=None, mode: str = "fused", batch: i
     if own:
         conv.close()
     return res
+
+
+def gpu_streams_graph(wl, dtype: str = "f32", batch: int = 64, channels=None, tune: bool = True):
+    """The benchmark's launch configuration: calls of `batch` blocks (max_batch
+    = batch, batched schedule autotuned), captured once as a HIP graph on a
+    side stream and replayed. Returns [len(channels)][n_calls*L] float64."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        conv = make_convolver(wl, dtype, stream=stream, max_batch=batch)
+        if tune:
+            conv.autotune_batch(iters=2)
+        x = torch.from_numpy(wl.padded_input()).cuda()
+        sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
+        out = torch.zeros((wl.n_channels, wl.n_calls * wl.hop), device="cuda")
+        stream.synchronize()
+        conv.capture_begin()
+        conv.process(x, sched, out, batch=batch)
+        conv.capture_end()
+        conv.reset()
+        conv.graph_launch()
+        stream.synchronize()
+        chans = list(range(wl.n_channels)) if channels is None else list(channels)
+        res = out[chans].cpu().numpy().astype(np.float64)
+        conv.close()
+    return res
+

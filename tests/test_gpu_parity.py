@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_common import gpu_streams, log, make_convolver, oracle_streams, rel_rms_per_channel
+from gpu_common import gpu_streams, gpu_streams_graph, log, make_convolver, oracle_streams, rel_rms_per_channel
 
 pytestmark = pytest.mark.gpu
 
@@ -254,6 +254,56 @@ def test_full_uneven_workload_sampled_channels():
     lens = wl.taps_of_channel
     chans = sorted({int(np.argmax(lens)), int(np.argmin(lens)), 0, 255, 511})
     _check(wl, channels=chans, name="uneven-full")
+
+
+# the benchmark's launch configuration: 64-block calls replayed from a HIP graph
+
+def test_full_binaural_bench_configuration():
+    log("full binaural, 64-block calls from a graph")
+    wl = synth.binaural()
+    chans = [0, 1, 62, 63, 126, 127]
+    got = gpu_streams_graph(wl, batch=64, channels=chans)
+    err = rel_rms_per_channel(got, oracle_streams(wl, chans))
+    log(f"binaural bench configuration: max rel-RMS {err.max():.3e}")
+    assert err.max() <= TOL_F32
+
+
+def test_full_binaural_bf16_bench_configuration():
+    log("full binaural bf16, 64-block calls from a graph")
+    wl = synth.binaural()
+    chans = [0, 63, 127]
+    got = gpu_streams_graph(wl, "bf16", batch=64, channels=chans)
+    err_q = rel_rms_per_channel(got, oracle_streams(wl, chans, dtype="bf16"))
+    snr = -20 * np.log10(rel_rms_per_channel(got, oracle_streams(wl, chans)))
+    log(f"binaural bf16 bench configuration: rel-RMS vs rounded oracle {err_q.max():.3e}, SNR min {snr.min():.1f} dB")
+    assert err_q.max() <= 2e-4 and snr.min() >= 40.0
+
+
+def test_full_uneven_bench_configuration():
+    log("full uneven, 64-block calls from a graph")
+    wl = synth.uneven()
+    lens = wl.taps_of_channel
+    chans = sorted({int(np.argmax(lens)), int(np.argmin(lens)), 0, 255, 511})
+    got = gpu_streams_graph(wl, batch=64, channels=chans)
+    err = rel_rms_per_channel(got, oracle_streams(wl, chans))
+    log(f"uneven bench configuration: max rel-RMS {err.max():.3e}")
+    assert err.max() <= TOL_F32
+
+
+@pytest.mark.parametrize("time_block", [8, 16])
+@pytest.mark.parametrize("batch", [64, 37, 23])
+def test_large_batches_several_time_groups(batch, time_block):
+    """Calls with several time groups per parity class, a partial last group
+    and a ragged last call."""
+    log(f"large batch {batch} time block {time_block}")
+    wl = synth.random_small(seed=77, hop=128, n_channels=7, n_inputs=3, n_samples=128 * 150 + 9,
+                            taps_range=(300, 9000), n_slots=3, p_switch=0.3)
+    conv = make_convolver(wl, max_batch=64)
+    conv.configure_batch(vec=1, time_block=time_block)
+    assert conv.info()["batch_time_block"] == time_block
+    got = gpu_streams(wl, conv=conv, batch=batch)
+    conv.close()
+    assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
 
 
 # ------------------------------------------------------------------ batched blocks
