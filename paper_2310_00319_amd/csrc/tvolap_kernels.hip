@@ -573,6 +573,9 @@ __global__ __launch_bounds__(256) void k_batch_spectra(DevPlan P, const float* _
 // slots per pass (blocks of further slots take further passes).
 enum TmacPattern { kOneSlot = 1, kAlternating = 2, kSelect = 3 };
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // f(integral_constant<int, i>) for i = 0 .. n-1, unrolled at compile time.
@@ -590,7 +593,7 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
   using ST = typename Store<DT>::T;
   constexpr int N = 2 * L;
   const int TW = B.tile_width;   // 64 V bins per wave, blockDim.x / 64 waves
-  constexpr int PD = 4;   // partitions loaded ahead
+  constexpr int PD = (TB == 16 && DT != 0) ? 8 : 4;   // partitions loaded ahead
   const DevPlan& P = B.P;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -678,31 +681,79 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
       constexpr int PAT = decltype(patc)::value;
       constexpr bool DCW = decltype(dcwc)::value;
       constexpr int ND = (PAT == kOneSlot) ? 1 : 2;
-      float2 X[TB][V];
+      // f32 storage: values as float2, four FMAs per complex product. 16-bit
+      // storage: raw words (Re in the low half, Im in the high half) and two
+      // packed dot products with FP32 accumulation per complex product:
+      // Re += (h.re, -h.im).(x.re, x.im), Im += (h.re, h.im).(x.im, x.re); every
+      // delay-line word in the window is kept beside its half-swapped copy.
+      using HW = std::conditional_t<DT == 0, float2, uint32_t>;   // loaded value
+      using XW = std::conditional_t<DT == 0, float2, uint2>;      // window entry
+      auto load_raw = [&](const ST* p, HW (&o)[V]) {
+        if constexpr (DT == 0) {
+          load_vec<0, V>(p, o);
+        } else if constexpr (V == 1) {
+          o[0] = *reinterpret_cast<const uint32_t*>(p);
+        } else {
+          const uint2 t = *reinterpret_cast<const uint2*>(p);
+          o[0] = t.x;
+          o[1] = t.y;
+        }
+      };
+      // window entry of a loaded delay-line value (v: bin within the lane)
+      auto entry = [&](const HW& w, int v) -> XW {
+        if constexpr (DT == 0) {
+          return w;
+        } else {
+          // on the DC lane the products are component-wise: no swap
+          const bool keep = DCW && v == 0 && dc_lane;
+          return make_uint2(w, keep ? w : __builtin_amdgcn_alignbit(w, w, 16));
+        }
+      };
+      XW X[TB][V];
 #pragma unroll
       for (int b = 0; b < TB; ++b) {
         int r = q0 + min(b, nb - 1) - m0;
         r = r < 0 ? r + Mi : (r >= Mi ? r - Mi : r);
-        load_vec<DT, V>(xbase + (uint32_t)r * N + kb, X[b]);
+        HW w[V];
+        load_raw(xbase + (uint32_t)r * N + kb, w);
+#pragma unroll
+        for (int v = 0; v < V; ++v) X[b][v] = entry(w[v], v);
       }
-      float2 Hq[PD][G][ND][V];
-      float2 Xq[PD][V];
-      auto load_h = [&](float2 (&Hs)[G][ND][V], int mm) {
+      HW Hq[PD][G][ND][V];
+      HW Xq[PD][V];
+      auto load_h = [&](HW (&Hs)[G][ND][V], int mm) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
           const int mr = min(mm, mlast[g]);
 #pragma unroll
-          for (int d = 0; d < ND; ++d) load_vec<DT, V>(hr[g][d] + (uint32_t)mr * N + kb, Hs[g][d]);
+          for (int d = 0; d < ND; ++d) load_raw(hr[g][d] + (uint32_t)mr * N + kb, Hs[g][d]);
         }
       };
-      auto load_x = [&](float2 (&Xs)[V], int mm) {   // delay-line row of partition mm for block 0
+      auto load_x = [&](HW (&Xs)[V], int mm) {   // delay-line row of partition mm for block 0
         int r = q0 - min(mm, m1 - 1);
         r = r < 0 ? r + Mi : r;
-        load_vec<DT, V>(xbase + (uint32_t)r * N + kb, Xs);
+        load_raw(xbase + (uint32_t)r * N + kb, Xs);
+      };
+      // acc += h x for one (channel, block, bin); hp: the prepared h terms
+      auto mac = [&](float2& a, const auto& hp, const XW& x) {
+        if constexpr (DT == 0) {
+          a.x = fmaf(hp[0], x.x, a.x);
+          a.x = fmaf(hp[1], x.y, a.x);
+          a.y = fmaf(hp[2], x.y, a.y);
+          a.y = fmaf(hp[3], x.x, a.y);
+        } else if constexpr (DT == 1) {
+          a.x = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, hp[0]), __builtin_bit_cast(bf16x2_t, x.x),
+                                                a.x, false);
+          a.y = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, hp[1]), __builtin_bit_cast(bf16x2_t, x.y),
+                                                a.y, false);
+        } else {
+          a.x = __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, hp[0]), __builtin_bit_cast(f16x2_t, x.x), a.x, false);
+          a.y = __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, hp[1]), __builtin_bit_cast(f16x2_t, x.y), a.y, false);
+        }
       };
       // partition mm = m0 + t (t = step index): accumulate, using X rows at
       // circular offset t
-      auto step = [&](const float2 (&Hs)[G][ND][V], int mm, auto tc) {
+      auto step = [&](const HW (&Hs)[G][ND][V], int mm, auto tc) {
         constexpr int T0 = decltype(tc)::value;   // t mod TB
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -711,14 +762,24 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
             for (int d = 0; d < ND; ++d) {
 #pragma unroll
               for (int v = 0; v < V; ++v) {
-                // complex product terms; on the DC lane (packed Re X(0),
+                // the h terms of the product; on the DC lane (packed Re X(0),
                 // Re X(2L)) the product is component-wise
-                const float2 h = Hs[g][d][v];
-                float hx = h.x, hny = -h.y, hx2 = h.x, hy2 = h.y;
-                if (DCW && v == 0) {
-                  hny = dc_lane ? 0.f : -h.y;
-                  hx2 = dc_lane ? h.y : h.x;
-                  hy2 = dc_lane ? 0.f : h.y;
+                const HW h = Hs[g][d][v];
+                std::conditional_t<DT == 0, float[4], uint32_t[2]> hp;
+                if constexpr (DT == 0) {
+                  hp[0] = h.x; hp[1] = -h.y; hp[2] = h.x; hp[3] = h.y;
+                  if (DCW && v == 0) {
+                    hp[1] = dc_lane ? 0.f : -h.y;
+                    hp[2] = dc_lane ? h.y : h.x;
+                    hp[3] = dc_lane ? 0.f : h.y;
+                  }
+                } else {
+                  hp[0] = h ^ 0x80000000u;
+                  hp[1] = h;
+                  if (DCW && v == 0) {
+                    hp[0] = dc_lane ? (h & 0xffffu) : hp[0];
+                    hp[1] = dc_lane ? (h & 0xffff0000u) : hp[1];
+                  }
                 }
 #pragma unroll
                 for (int b = 0; b < TB; ++b) {
@@ -727,21 +788,13 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
                   else if constexpr (PAT == kAlternating) use = ((b & 1) == d);
                   else use = true;
                   if (use) {
-                    const float2 x = X[(b - T0 + TB) % TB][v];
+                    const XW& x = X[(b - T0 + TB) % TB][v];
                     if constexpr (PAT == kSelect) {
                       // uniform per (g, b): slot d of this pass, or nothing
                       const bool on = ((take[g] >> b) & 1u) && ((((sel1[g] >> b) & 1u) != 0u) == (d == 1));
-                      if (on) {
-                        acc[g][b][v].x = fmaf(hx, x.x, acc[g][b][v].x);
-                        acc[g][b][v].x = fmaf(hny, x.y, acc[g][b][v].x);
-                        acc[g][b][v].y = fmaf(hx2, x.y, acc[g][b][v].y);
-                        acc[g][b][v].y = fmaf(hy2, x.x, acc[g][b][v].y);
-                      }
+                      if (on) mac(acc[g][b][v], hp, x);
                     } else {
-                      acc[g][b][v].x = fmaf(hx, x.x, acc[g][b][v].x);
-                      acc[g][b][v].x = fmaf(hny, x.y, acc[g][b][v].x);
-                      acc[g][b][v].y = fmaf(hx2, x.y, acc[g][b][v].y);
-                      acc[g][b][v].y = fmaf(hy2, x.x, acc[g][b][v].y);
+                      mac(acc[g][b][v], hp, x);
                     }
                   }
                 }
@@ -763,7 +816,7 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
         step(Hq[t % PD], mm, tc);
         load_h(Hq[t % PD], mm + PD);
 #pragma unroll
-        for (int v = 0; v < V; ++v) X[(TB - 1 - t) % TB][v] = Xq[t % PD][v];
+        for (int v = 0; v < V; ++v) X[(TB - 1 - t) % TB][v] = entry(Xq[t % PD][v], v);
         load_x(Xq[t % PD], mm + 1 + PD);
       };
       int mb = m0;
