@@ -524,37 +524,49 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
 // order. The delay line holds M_i + (n_max-1)/2 spectra per parity, so a
 // batch's new spectra never replace ones that its own blocks still read.
 
-// Spectrum of input i for block j of the batch (block j's 2L samples are the
+// Blocks per workgroup in the batched transform kernels (their twiddle and
+// window tables are loaded once per workgroup).
+constexpr int kBatchBlocksPerWg = 4;
+
+// Spectra of input i for blocks j of the batch (block j's 2L samples are the
 // previous call's L samples, from the history for j = 0, then its own L).
 template <int L, int DT>
 __global__ __launch_bounds__(256) void k_batch_spectra(DevPlan P, const float* __restrict__ in, int64_t in_stride,
                                                        const float* __restrict__ hist,
                                                        typename Store<DT>::T* __restrict__ fdl,
-                                                       const uint64_t* __restrict__ counter) {
+                                                       const uint64_t* __restrict__ counter, int n_blocks) {
   constexpr int N = 2 * L;
   constexpr int T = 256;
   __shared__ float2 twl[2 * N];
   __shared__ float winl[N];
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
-  const int j = blockIdx.x, i = blockIdx.y, tid = threadIdx.x;
-  const uint64_t cnt = *counter + (uint64_t)j;
-  const int p = (int)(cnt & 1u);
-  load_tables<L, T>(P, twl, winl, tid);
-  const float* xin = in + (int64_t)i * in_stride + (int64_t)j * L;
-  const float* hold = (j == 0) ? hist + ((size_t)(p ^ 1) * P.I + i) * L : xin - L;
-  for (int n = tid; n < L; n += T) {
-    const int t0 = 2 * n, t1 = 2 * n + 1;
-    const float s0 = (t0 < L) ? hold[t0] : xin[t0 - L];
-    const float s1 = (t1 < L) ? hold[t1] : xin[t1 - L];
-    bufA[n] = make_float2(P.win[t0] * s0, P.win[t1] * s1);
-    bufA[n + L] = make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  const float2* Z = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+  const int i = blockIdx.y, tid = threadIdx.x;
+  const uint64_t cnt0 = *counter;
   const int Mi = P.in_M[i];
-  typename Store<DT>::T* dst = fdl + P.in_fdl_off[i] + ((int64_t)p * Mi + ring_slot(cnt, Mi)) * N;
-  for (int k = tid; k < N; k += T) dst[k] = pack<DT>(fft::real_fwd_post<N>(Z, k, twl));
+  load_tables<L, T>(P, twl, winl, tid);
+  __syncthreads();
+  // kBatchBlocksPerWg consecutive blocks per workgroup (tables loaded once)
+  for (int u = 0; u < kBatchBlocksPerWg; ++u) {
+    const int j = blockIdx.x * kBatchBlocksPerWg + u;
+    if (j >= n_blocks) break;
+    const uint64_t cnt = cnt0 + (uint64_t)j;
+    const int p = (int)(cnt & 1u);
+    const float* xin = in + (int64_t)i * in_stride + (int64_t)j * L;
+    const float* hold = (j == 0) ? hist + ((size_t)(p ^ 1) * P.I + i) * L : xin - L;
+    for (int n = tid; n < L; n += T) {
+      const int t0 = 2 * n, t1 = 2 * n + 1;
+      const float s0 = (t0 < L) ? hold[t0] : xin[t0 - L];
+      const float s1 = (t1 < L) ? hold[t1] : xin[t1 - L];
+      bufA[n] = make_float2(winl[t0] * s0, winl[t1] * s1);
+      bufA[n + L] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const float2* Z = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
+    typename Store<DT>::T* dst = fdl + P.in_fdl_off[i] + ((int64_t)p * Mi + ring_slot(cnt, Mi)) * N;
+    for (int k = tid; k < N; k += T) dst[k] = pack<DT>(fft::real_fwd_post<N>(Z, k, twl));
+    __syncthreads();
+  }
 }
 
 // Spectral MAC of a batch (eq. 8), blocked in time. Blocks of one parity
@@ -919,28 +931,34 @@ __global__ __launch_bounds__(256) void k_batch_inv(BatchArgs B) {
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
   const DevPlan& P = B.P;
-  const int c = blockIdx.x, j = blockIdx.y, tid = threadIdx.x;
+  const int c = blockIdx.x, tid = threadIdx.x;
   load_tables<L, T>(P, twl, winl, tid);
   const int TW = B.tile_width;
   const int base = B.row_base[c];
   const int nch = B.nchunks[c];
-  const float2* yp = B.ypart + (int64_t)j * B.n_rows * TW;
-  for (int k = tid; k < N; k += T) {
-    const int t = k / TW;
-    const int kk = k - t * TW;
-    const float2* src = yp + ((int64_t)base + (int64_t)t * nch) * TW + kk;
-    float2 s0 = src[0];
-    float2 s1 = make_float2(0.f, 0.f);
-    int q = 1;
-    for (; q + 1 < nch; q += 2) {
-      s0 = cadd(s0, src[(int64_t)q * TW]);
-      s1 = cadd(s1, src[(int64_t)(q + 1) * TW]);
+  // kBatchBlocksPerWg consecutive blocks per workgroup (tables loaded once)
+  for (int u = 0; u < kBatchBlocksPerWg; ++u) {
+    const int j = blockIdx.y * kBatchBlocksPerWg + u;
+    if (j >= B.n_blocks) break;
+    const float2* yp = B.ypart + (int64_t)j * B.n_rows * TW;
+    for (int k = tid; k < N; k += T) {
+      const int t = k / TW;
+      const int kk = k - t * TW;
+      const float2* src = yp + ((int64_t)base + (int64_t)t * nch) * TW + kk;
+      float2 s0 = src[0];
+      float2 s1 = make_float2(0.f, 0.f);
+      int q = 1;
+      for (; q + 1 < nch; q += 2) {
+        s0 = cadd(s0, src[(int64_t)q * TW]);
+        s1 = cadd(s1, src[(int64_t)(q + 1) * TW]);
+      }
+      if (q < nch) s0 = cadd(s0, src[(int64_t)q * TW]);
+      Y[k] = cadd(s0, s1);
     }
-    if (q < nch) s0 = cadd(s0, src[(int64_t)q * TW]);
-    Y[k] = cadd(s0, s1);
+    __syncthreads();
+    inverse_store<L, T>(Y, bufA, bufB, twl, B.yblk + ((int64_t)j * P.C + c) * 4 * L, tid);
+    __syncthreads();
   }
-  __syncthreads();
-  inverse_store<L, T>(Y, bufA, bufB, twl, B.yblk + ((int64_t)j * P.C + c) * 4 * L, tid);
 }
 
 // Overlap-add of the batch's n blocks (eq. 10-13 in the two-step form), grid
@@ -963,7 +981,9 @@ __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __r
   const DevPlan& P = B.P;
   const int c = blockIdx.x, sw = blockIdx.y, tid = threadIdx.x;
   const int n = B.n_blocks;
-  const uint64_t cnt0 = *B.counter;
+  // only the workgroups of the first sample range read the call count (for
+  // the history parity); they alone count towards advancing it
+  const uint64_t cnt0 = (sw == 0) ? *B.counter : 0;
   __shared__ int last;
   if (c < P.C) {
     float* st = ola + (int64_t)c * 3 * L;
@@ -1033,8 +1053,8 @@ __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __r
     for (int k = tid; k < L; k += T) hnew[k] = xin[k];
   }
   __syncthreads();
-  if (tid == 0) {
-    if (atomicAdd(B.done, 1) == (int)(gridDim.x * gridDim.y) - 1) {
+  if (tid == 0 && sw == 0) {
+    if (atomicAdd(B.done, 1) == (int)gridDim.x - 1) {
       *B.done = 0;
       *B.counter = cnt0 + (uint64_t)n;
     }
@@ -1248,8 +1268,9 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
     using ST = typename Store<DT>::T;
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_batch_spectra<L, DT>), dim3(B.n_blocks, B.P.I), dim3(256), 0, s, B.P, in, in_stride,
-                       hist, static_cast<ST*>(B.fdl), B.counter);
+    const int bgroups = (B.n_blocks + kBatchBlocksPerWg - 1) / kBatchBlocksPerWg;
+    hipLaunchKernelGGL((k_batch_spectra<L, DT>), dim3(bgroups, B.P.I), dim3(256), 0, s, B.P, in, in_stride, hist,
+                       static_cast<ST*>(B.fdl), B.counter, B.n_blocks);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
@@ -1271,7 +1292,7 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
       if (e != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_batch_inv<L>), dim3(B.P.C, B.n_blocks), dim3(256), 0, s, B);
+    hipLaunchKernelGGL((k_batch_inv<L>), dim3(B.P.C, bgroups), dim3(256), 0, s, B);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int wgs = B.P.C > B.P.I ? B.P.C : B.P.I;
