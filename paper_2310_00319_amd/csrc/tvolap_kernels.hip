@@ -581,9 +581,10 @@ __global__ __launch_bounds__(256) void k_batch_spectra(DevPlan P, const float* _
 // partial spectrum row per partition chunk.
 
 // Slot pattern of an item's blocks, per channel: one slot for all blocks,
-// two slots alternating with the block index, or any assignment of up to two
-// slots per pass (blocks of further slots take further passes).
-enum TmacPattern { kOneSlot = 1, kAlternating = 2, kSelect = 3 };
+// two slots alternating with the block index, two slots in any order (each
+// block picks its slot's spectrum with a select), or any assignment of up to
+// two slots per pass (blocks of further slots take further passes).
+enum TmacPattern { kOneSlot = 1, kAlternating = 2, kSelect = 3, kTwoSlots = 4 };
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
@@ -662,14 +663,19 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
         const int sv = uniform(slot[g][b]);
         slot[g][b] = sv < 0 ? 0 : (sv >= P.K ? P.K - 1 : sv);
       }
-    bool one = true, alt = true;
+    bool one = true, alt = true, two_slots = true;
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+    for (int g = 0; g < G; ++g) {
+      int other = slot[g][0];
 #pragma unroll
       for (int b = 0; b < TB; ++b) {
         one = one && (slot[g][b] == slot[g][0]);
         alt = alt && (slot[g][b] == slot[g][b & 1]);
+        if (slot[g][b] != slot[g][0]) other = slot[g][b];
       }
+#pragma unroll
+      for (int b = 0; b < TB; ++b) two_slots = two_slots && (slot[g][b] == slot[g][0] || slot[g][b] == other);
+    }
     float2 acc[G][TB][V];
 #pragma unroll
     for (int g = 0; g < G; ++g)
@@ -771,7 +777,7 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
         for (int g = 0; g < G; ++g) {
           if (mm < Mc[g]) {
 #pragma unroll
-            for (int d = 0; d < ND; ++d) {
+            for (int d = 0; d < (PAT == kTwoSlots ? 1 : ND); ++d) {
 #pragma unroll
               for (int v = 0; v < V; ++v) {
                 // the h terms of the product; on the DC lane (packed Re X(0),
@@ -801,7 +807,30 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
                   else use = true;
                   if (use) {
                     const XW& x = X[(b - T0 + TB) % TB][v];
-                    if constexpr (PAT == kSelect) {
+                    if constexpr (PAT == kTwoSlots) {
+                      // slot 1 or slot 0 for this block: uniform select
+                      const bool s1 = ((sel1[g] >> b) & 1u) != 0u;
+                      decltype(hp) hq;
+                      const HW h1 = Hs[g][1][v];
+                      if constexpr (DT == 0) {
+                        const float a0 = s1 ? h1.x : h.x, a1 = s1 ? h1.y : h.y;
+                        hq[0] = a0; hq[1] = -a1; hq[2] = a0; hq[3] = a1;
+                        if (DCW && v == 0) {
+                          hq[1] = dc_lane ? 0.f : -a1;
+                          hq[2] = dc_lane ? a1 : a0;
+                          hq[3] = dc_lane ? 0.f : a1;
+                        }
+                      } else {
+                        const uint32_t w = s1 ? h1 : h;
+                        hq[0] = w ^ 0x80000000u;
+                        hq[1] = w;
+                        if (DCW && v == 0) {
+                          hq[0] = dc_lane ? (w & 0xffffu) : hq[0];
+                          hq[1] = dc_lane ? (w & 0xffff0000u) : hq[1];
+                        }
+                      }
+                      mac(acc[g][b][v], hq, x);
+                    } else if constexpr (PAT == kSelect) {
                       // uniform per (g, b): slot d of this pass, or nothing
                       const bool on = ((take[g] >> b) & 1u) && ((((sel1[g] >> b) & 1u) != 0u) == (d == 1));
                       if (on) mac(acc[g][b][v], hp, x);
@@ -854,6 +883,24 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
         if (dcw) run(std::integral_constant<int, kAlternating>{}, std::true_type{}, hr, none, none);
         else run(std::integral_constant<int, kAlternating>{}, std::false_type{}, hr, none, none);
       }
+    } else if (two_slots) {
+      const ST* hr[G][2];
+      uint32_t sel1[G], none[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        none[g] = 0u;
+        const int s0 = slot[g][0];
+        int s1v = s0;
+        uint32_t m1b = 0u;
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+          if (slot[g][b] != s0) { s1v = slot[g][b]; m1b |= 1u << b; }
+        sel1[g] = m1b;
+        hr[g][0] = hch[g] + (int64_t)s0 * McL[g] * N;
+        hr[g][1] = hch[g] + (int64_t)s1v * McL[g] * N;
+      }
+      if (dcw) run(std::integral_constant<int, kTwoSlots>{}, std::true_type{}, hr, sel1, none);
+      else run(std::integral_constant<int, kTwoSlots>{}, std::false_type{}, hr, sel1, none);
     } else {
       // passes of up to two slots per channel
       uint32_t todo[G];
