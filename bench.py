@@ -178,6 +178,7 @@ def main():
     ap.add_argument("--bvec", type=int, default=0, help="batched MAC: complex bins per lane (1 or 2)")
     ap.add_argument("--bwaves", type=int, default=0, help="batched MAC: waves per workgroup (1, 2 or 4)")
     ap.add_argument("--btb", type=int, default=0, help="batched MAC: blocks per time group (8 or 16)")
+    ap.add_argument("--bgroup", type=int, default=0, help="batched MAC: channels per work item (1 or 2)")
     ap.add_argument("--no-realtime", action="store_true",
                     help="skip the extra one-block-per-call measurement")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
@@ -286,8 +287,9 @@ def run(args, spec, wl, stream):
     t_setir = time.perf_counter() - t0
     tuned_us = None
     tuned_batch_us = None
-    if args.batch > 1 and (args.bchunk or args.bvec or args.bwaves or args.btb):
-        conv.configure_batch(chunk=args.bchunk, vec=args.bvec, waves=args.bwaves, time_block=args.btb)
+    if args.batch > 1 and (args.bchunk or args.bvec or args.bwaves or args.btb or args.bgroup):
+        conv.configure_batch(chunk=args.bchunk, vec=args.bvec, waves=args.bwaves, time_block=args.btb,
+                             group=args.bgroup)
     elif args.batch > 1 and not args.no_autotune:
         t0 = time.perf_counter()
         tuned_batch_us = conv.autotune_batch(iters=3)
@@ -502,7 +504,7 @@ def run(args, spec, wl, stream):
                      "waves": info["mac_waves"], "grid": info["mac_grid"], "work_items": info["n_work_items"],
                      "autotuned_us_per_block": tuned_us,
                      "batch": {"chunk": info["batch_chunk"], "vec": info["batch_vec"], "waves": info["batch_waves"],
-                               "time_block": info["batch_time_block"],
+                               "time_block": info["batch_time_block"], "group": info["batch_group"],
                                "tile_width": info["batch_tile_width"], "work_items": info["batch_work_items"],
                                "autotuned_us_per_block": tuned_batch_us}},
     }

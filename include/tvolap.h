@@ -97,6 +97,7 @@ typedef struct {
                                        batch_time_block blocks of a call)                */
   int32_t batch_rows;               /* partial-spectrum rows per block                   */
   int32_t batch_time_block;         /* blocks of one parity per time group (8 or 16)     */
+  int32_t batch_group;              /* channels of one input per work item (1 or 2)      */
 } tvolap_info;
 
 /* Create a convolver (Sec. 2: partitioned, block-synchronously switchable,
@@ -207,13 +208,16 @@ int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us);
  * per compute unit); vec: complex bins per lane (1 or 2; 0 = 2, or 1 with time
  * groups of 16); waves: 1, 2 or 4 waves per workgroup, each owning 64 vec bins
  * (0 = 4, fewer when 2L bins are fewer); time_block: 8 or 16 (16 needs vec 1;
- * 0 = 16 when max_batch >= 32, else 8). Waits for the stream; rebuilds the
- * batched work list. Errors: EINVAL, ESTATE during capture, ENOMEM/EDEVICE. */
-int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block);
+ * 0 = 16 when max_batch >= 32, else 8); group: channels of one input per work
+ * item, 1 or 2 (two channels share the delay-line loads; 0 = 2 when an input
+ * feeds several channels). Waits for the stream; rebuilds the batched work
+ * list. Errors: EINVAL, ESTATE during capture, ENOMEM/EDEVICE. */
+int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block,
+                           int32_t group);
 
 /* Autotuner for batched calls: times `iters` calls of max_batch blocks (zero
  * input, current bank, block b of the batch in slot b mod K) for each
- * candidate (time_block, vec, waves, chunk), keeps the fastest, caches it for handles of
+ * candidate (group, time_block, vec, waves, chunk), keeps the fastest, caches it for handles of
  * the same shape and max_batch in this process, then resets the stream state
  * as tvolap_reset does. *best_us (may be NULL) receives the best time per
  * block in microseconds, or -1 when the choice came from the cache.

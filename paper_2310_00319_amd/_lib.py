@@ -86,6 +86,7 @@ class TvolapInfo(ctypes.Structure):
         ("batch_work_items", ctypes.c_int32),
         ("batch_rows", ctypes.c_int32),
         ("batch_time_block", ctypes.c_int32),
+        ("batch_group", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -132,7 +133,7 @@ def _declare(lib):
     lib.tvolap_last_error.restype = ctypes.c_char_p
     lib.tvolap_configure.argtypes = [c_vp, c_i32, c_i32, c_i32, c_i32]
     lib.tvolap_autotune.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_float)]
-    lib.tvolap_configure_batch.argtypes = [c_vp, c_i32, c_i32, c_i32, c_i32]
+    lib.tvolap_configure_batch.argtypes = [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32]
     lib.tvolap_autotune_batch.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_float)]
     lib.tvolap_capture_begin.argtypes = [c_vp]
     lib.tvolap_capture_end.argtypes = [c_vp]

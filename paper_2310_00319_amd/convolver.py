@@ -183,10 +183,10 @@ class Convolver:
         check(self._lib.tvolap_autotune(self._h, int(iters), ctypes.byref(best)), self._h)
         return best.value
 
-    def configure_batch(self, chunk: int = 0, vec: int = 0, waves: int = 0, time_block: int = 0):
+    def configure_batch(self, chunk: int = 0, vec: int = 0, waves: int = 0, time_block: int = 0, group: int = 0):
         """Schedule of batched calls (process with batch > 1)."""
-        check(self._lib.tvolap_configure_batch(self._h, int(chunk), int(vec), int(waves), int(time_block)),
-              self._h)
+        check(self._lib.tvolap_configure_batch(self._h, int(chunk), int(vec), int(waves), int(time_block),
+                                               int(group)), self._h)
 
     def autotune_batch(self, iters: int = 5) -> float:
         best = ctypes.c_float()

@@ -47,7 +47,7 @@ struct MacChoice {
 // (0 = automatic), complex bins per lane (0 = automatic), waves per tile
 // (0 = automatic).
 struct BatchChoice {
-  int32_t chunk = 0, vec = 0, waves = 0, time_block = 0;
+  int32_t chunk = 0, vec = 0, waves = 0, time_block = 0, group = 0;
 };
 
 // Autotuner results, keyed by the handle's shape (hop, channels, inputs,
@@ -358,7 +358,7 @@ void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   for (int c = 0; c < h->C; ++c) by_input[h->ch_input[c]].push_back(c);
   int fan = 1;
   for (auto& v : by_input) fan = std::max<int>(fan, (int)v.size());
-  const int G = fan >= 2 ? 2 : 1;
+  const int G = (fan >= 2 && bc.group != 1) ? 2 : 1;
   h->bshape.G = G;
   struct Sub { int input; std::vector<int> ch; int M; };
   std::vector<Sub> subs;
@@ -459,6 +459,7 @@ int apply_batch_choice(tvolap_t* h, const BatchChoice& c) {
   h->bchoice.vec = h->bshape.V;
   h->bchoice.waves = h->bshape.NW;
   h->bchoice.time_block = h->b_tb;
+  h->bchoice.group = h->bshape.G;
   return TVOLAP_OK;
 }
 
@@ -899,7 +900,8 @@ int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, i
   return apply_choice(h, c);
 }
 
-int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block) {
+int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block,
+                           int32_t group) {
   if (!h) return TVOLAP_EINVAL;
   if (h->capturing) return fail(h, TVOLAP_ESTATE, "cannot reconfigure during graph capture");
   if (chunk < 0) return fail(h, TVOLAP_EINVAL, "chunk must be >= 0");
@@ -908,11 +910,13 @@ int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t wave
   if (time_block != 0 && time_block != 8 && time_block != 16)
     return fail(h, TVOLAP_EINVAL, "time_block must be 0, 8 or 16");
   if (time_block == 16 && vec == 2) return fail(h, TVOLAP_EINVAL, "time_block 16 needs vec 1");
+  if (group != 0 && group != 1 && group != 2) return fail(h, TVOLAP_EINVAL, "group must be 0, 1 or 2");
   BatchChoice c;
   c.chunk = chunk;
   c.vec = vec;
   c.waves = waves;
   c.time_block = time_block;
+  c.group = group;
   return apply_batch_choice(h, c);
 }
 
@@ -964,6 +968,14 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
   float best_t = 1e30f;
   int rc = TVOLAP_OK;
   const std::vector<int> vecs = {1, 2};
+  int fan = 1;
+  {
+    std::vector<int> cnt(h->I, 0);
+    for (int c = 0; c < h->C; ++c) fan = std::max(fan, ++cnt[h->ch_input[c]]);
+  }
+  std::vector<int> groups = {fan >= 2 ? 2 : 1};
+  if (fan >= 2) groups.push_back(1);
+  for (int grp : groups)
   for (int tb : tbs)
   for (int vec : vecs) {
     if (tb == 16 && vec != 1) continue;
@@ -984,6 +996,7 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
         c.vec = vec;
         c.waves = nw;
         c.time_block = tb;
+        c.group = grp;
         rc = apply_batch_choice(h, c);
         if (rc != TVOLAP_OK) break;
         // every block of the batch selects slot (block mod K), as a switching stream does
@@ -1195,6 +1208,7 @@ int tvolap_get_info(const tvolap_t* h, tvolap_info* info) {
   info->batch_work_items = h->n_bmac;
   info->batch_rows = h->n_brows;
   info->batch_time_block = h->b_tb;
+  info->batch_group = h->bshape.G;
   info->n_cu = h->n_cu;
   return TVOLAP_OK;
 }

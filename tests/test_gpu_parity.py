@@ -328,20 +328,22 @@ def test_batched_blocks_match_single_blocks(case, batch):
 # chunk; cases with up to four distinct slots among the blocks of a time group
 # (several slot passes), ragged partition counts within a channel group and
 # partial time groups (batch 11)
-BATCH_SCHEDULES = [(0, 0, 0), (2, 1, 1), (3, 2, 2), (1, 2, 4), (200, 1, 2), (5, 2, 1)]
+BATCH_SCHEDULES = [(0, 0, 0, 0), (2, 1, 1, 0), (3, 2, 2, 0), (1, 2, 4, 1), (200, 1, 2, 1), (5, 2, 1, 1)]
 
 
-@pytest.mark.parametrize("sched", BATCH_SCHEDULES, ids=[f"c{s[0]}v{s[1]}w{s[2]}" for s in BATCH_SCHEDULES])
+@pytest.mark.parametrize("sched", BATCH_SCHEDULES, ids=[f"c{s[0]}v{s[1]}w{s[2]}g{s[3]}" for s in BATCH_SCHEDULES])
 @pytest.mark.parametrize("case", [SMALL_CASES[1], SMALL_CASES[4], SMALL_CASES[3]], ids=["s2_L128", "s5_L64", "s4_L512"])
 def test_batch_schedules(case, sched):
     seed, L, C, I, N, tr, K, p = case
-    chunk, vec, waves = sched
+    chunk, vec, waves, group = sched
     log(f"batch schedule {sched} case {case}")
     wl = synth.random_small(seed=seed + 100, hop=L, n_channels=C, n_inputs=I, n_samples=N,
                             taps_range=tr, n_slots=K, p_switch=max(p, 0.6))
     conv = make_convolver(wl)
-    conv.configure_batch(chunk=chunk, vec=vec, waves=waves)
+    conv.configure_batch(chunk=chunk, vec=vec, waves=waves, group=group)
     info = conv.info()
+    if group:
+        assert info["batch_group"] == group or (group == 2 and info["batch_group"] == 1)
     assert info["batch_tile_width"] == 64 * info["batch_vec"] * info["batch_waves"]
     got = gpu_streams(wl, conv=conv, batch=11)
     conv.close()
