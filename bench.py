@@ -179,6 +179,7 @@ def main():
     ap.add_argument("--bwaves", type=int, default=0, help="batched MAC: waves per workgroup (1, 2 or 4)")
     ap.add_argument("--btb", type=int, default=0, help="batched MAC: blocks per time group (8 or 16)")
     ap.add_argument("--bgroup", type=int, default=0, help="batched MAC: channels per work item (1 or 2)")
+    ap.add_argument("--no-ingest", action="store_true", help="skip the IR-bank ingestion timing")
     ap.add_argument("--no-realtime", action="store_true",
                     help="skip the extra one-block-per-call measurement")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
@@ -285,6 +286,36 @@ def run(args, spec, wl, stream):
             conv.set_ir(c, s, wl.taps[c][s])
     torch.cuda.synchronize()
     t_setir = time.perf_counter() - t0
+    info0 = conv.info()
+    # IR-bank ingestion: every slot of every channel again, one launch per
+    # slot from device taps (writes the same spectra)
+    ingest = None
+    if not args.no_ingest:
+        rows = []
+        for k in range(wl.n_slots):
+            r = np.zeros((wl.n_channels, wl.max_taps()), np.float32)
+            for c in range(wl.n_channels):
+                t = wl.taps[c][k]
+                r[c, :len(t)] = t
+            rows.append(torch.from_numpy(r).cuda())
+        for k in range(wl.n_slots):
+            conv.set_irs(k, rows[k])
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 3
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            for k in range(wl.n_slots):
+                conv.set_irs(k, rows[k])
+        e1.record()
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / (reps * wl.n_slots)
+        parts = info0["sum_partitions"]
+        ingest = {"us_per_slot_all_channels": round(us, 2), "partitions_per_slot": int(parts),
+                  "partition_transforms_per_s": round(parts / (us * 1e-6), 1),
+                  "taps_per_s": round(parts * 2 * wl.hop / (us * 1e-6), 1)}
+        del rows
     tuned_us = None
     tuned_batch_us = None
     if args.batch > 1 and (args.bchunk or args.bvec or args.bwaves or args.btb or args.bgroup):
@@ -497,6 +528,7 @@ def run(args, spec, wl, stream):
         "cpu_baseline": cpu,
         "accuracy": accuracy,
         "ir_bank_load_s": round(t_setir, 3),
+        "ir_bank_ingest": ingest,
         "graph": bool(args.graph),
         "blocks_per_call": args.batch,
         "realtime_one_block_per_call": realtime,

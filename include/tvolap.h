@@ -128,6 +128,16 @@ int tvolap_destroy(tvolap_t* h);
 int tvolap_set_ir(tvolap_t* h, int32_t channel, int32_t slot, const float* taps,
                   int32_t n_taps, int32_t taps_on_device);
 
+/* Load slot `slot` of every channel in one launch (Sec. 2, eq. 3, 5, 7, as
+ * tvolap_set_ir does per channel): channel c's taps are
+ * taps_dev[c*taps_stride + t] (device memory, read in stream order), t <
+ * min(taps_stride, taps of channel c); the rest of its partitions are zero.
+ * For whole-bank loads and for impulse responses that change at every block
+ * (head tracking), followed by a selection of that slot. Asynchronous; may
+ * be recorded in a graph. Errors: EINVAL (slot out of range, NULL taps,
+ * taps_stride < 1), EDEVICE. */
+int tvolap_set_irs(tvolap_t* h, int32_t slot, const float* taps_dev, int64_t taps_stride);
+
 /* Select the active slot of every channel (end of Sec. 2: all partitions of a
  * channel switch together). `slot_of_channel` is a host array [C] with values
  * in [0, K); it is copied before the call returns and applies from the next

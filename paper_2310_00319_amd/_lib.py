@@ -26,7 +26,7 @@ TVOLAP_ESTATE = -4
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 
 EXPORTED = (
-    "tvolap_create", "tvolap_destroy", "tvolap_set_ir", "tvolap_select_ir",
+    "tvolap_create", "tvolap_destroy", "tvolap_set_ir", "tvolap_set_irs", "tvolap_select_ir",
     "tvolap_process_block", "tvolap_process_blocks", "tvolap_reset", "tvolap_get_info", "tvolap_get_partitions",
     "tvolap_set_timing", "tvolap_get_timing", "tvolap_last_error", "tvolap_version",
     "tvolap_configure", "tvolap_autotune", "tvolap_configure_batch", "tvolap_autotune_batch",
@@ -120,6 +120,7 @@ def _declare(lib):
     lib.tvolap_create.argtypes = [ctypes.POINTER(TvolapConfig), ctypes.POINTER(c_vp)]
     lib.tvolap_destroy.argtypes = [c_vp]
     lib.tvolap_set_ir.argtypes = [c_vp, c_i32, c_i32, c_vp, c_i32, c_i32]
+    lib.tvolap_set_irs.argtypes = [c_vp, c_i32, c_vp, c_i64]
     lib.tvolap_select_ir.argtypes = [c_vp, c_vp]
     lib.tvolap_process_block.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp]
     lib.tvolap_process_blocks.argtypes = [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64, c_vp, c_i64]

@@ -105,6 +105,16 @@ class Convolver:
         check(self._lib.tvolap_set_ir(self._h, int(channel), int(slot), a.ctypes.data_as(ctypes.c_void_p),
                                       int(a.shape[0]), 0), self._h)
 
+    def set_irs(self, slot: int, taps: torch.Tensor):
+        """Load slot `slot` of every channel in one launch from a contiguous CUDA
+        float32 tensor [n_channels][n] (row c: taps of channel c; taps beyond
+        a channel's length are ignored, missing ones are zero)."""
+        if not isinstance(taps, torch.Tensor) or not taps.is_cuda or taps.dtype != torch.float32 \
+                or taps.dim() != 2 or taps.shape[0] != self.n_channels or not taps.is_contiguous():
+            raise ValueError("taps must be a contiguous CUDA float32 tensor [n_channels][n]")
+        check(self._lib.tvolap_set_irs(self._h, int(slot), ctypes.c_void_p(taps.data_ptr()), int(taps.shape[1])),
+              self._h)
+
     def select_ir(self, slot_of_channel):
         a = _i32_host(slot_of_channel, self.n_channels, "slot_of_channel")
         check(self._lib.tvolap_select_ir(self._h, a.ctypes.data_as(ctypes.c_void_p)), self._h)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -94,6 +95,8 @@ struct tvolap {
   int32_t* d_tune_sel = nullptr;  // [K][C] autotuner selections (row k: every channel in slot k)
   int32_t* d_in_ch_ptr = nullptr; // [I+1]
   int32_t* d_in_ch = nullptr;     // [C]
+  int32_t* d_part_base = nullptr; // [C+1] prefix sums of the partition counts
+  int32_t* d_ch_taps = nullptr;   // [C] taps per channel
 
   // MAC work list
   MacShape shape{2, 1, 4};
@@ -219,7 +222,7 @@ void free_all(tvolap_t* h) {
   dfree(h->d_counter); dfree(h->d_tw); dfree(h->d_win); dfree(h->d_ch_input); dfree(h->d_ch_M);
   dfree(h->d_ch_bank_off); dfree(h->d_in_M); dfree(h->d_in_fdl_off); dfree(h->d_taps);
   dfree(h->d_arrive); dfree(h->d_done); dfree(h->d_zero_in); dfree(h->d_tune_out); dfree(h->d_tune_sel);
-  dfree(h->d_in_ch_ptr); dfree(h->d_in_ch); dfree(h->d_yblk); dfree(h->d_tune_bsel);
+  dfree(h->d_in_ch_ptr); dfree(h->d_in_ch); dfree(h->d_part_base); dfree(h->d_ch_taps); dfree(h->d_yblk); dfree(h->d_tune_bsel);
   if (h->events_made)
     for (auto& t : h->tsets)
       for (auto& e : t.ev) (void)hipEventDestroy(e);
@@ -550,6 +553,8 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_tune_bsel, (size_t)h->max_batch * h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_in_ch_ptr, (size_t)(h->I + 1) * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_in_ch, (size_t)h->C * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_part_base, (size_t)(h->C + 1) * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_ch_taps, (size_t)h->C * sizeof(int32_t)));
   {
     std::vector<int32_t> ts((size_t)h->K * h->C);
     for (int k = 0; k < h->K; ++k)
@@ -567,6 +572,10 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
     }
     HIP_TRY(h, hipMemcpy(h->d_in_ch_ptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(h->d_in_ch, chs.data(), chs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    std::vector<int32_t> pb(h->C + 1, 0);
+    for (int c = 0; c < h->C; ++c) pb[c + 1] = pb[c] + h->ch_M[c];
+    HIP_TRY(h, hipMemcpy(h->d_part_base, pb.data(), pb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->d_ch_taps, h->ch_taps.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
   }
 
   // twiddles exp(-2 pi i t / 4L) and the Hann window, evaluated in double precision
@@ -803,6 +812,19 @@ int tvolap_set_ir(tvolap_t* h, int32_t channel, int32_t slot, const float* taps,
   char* dst = static_cast<char*>(h->d_bank) +
               (size_t)(h->ch_bank_off[channel] + (int64_t)slot * M * N) * h->store_bytes;
   HIP_TRY(h, tvx::launch_irprep(h->plan(), h->dtype, src, n_taps, M, dst, h->stream));
+  return TVOLAP_OK;
+}
+
+int tvolap_set_irs(tvolap_t* h, int32_t slot, const float* taps_dev, int64_t taps_stride) {
+  if (!h) return TVOLAP_EINVAL;
+  if (slot < 0 || slot >= h->K) return fail(h, TVOLAP_EINVAL, "slot out of range");
+  if (!taps_dev) return fail(h, TVOLAP_EINVAL, "taps is NULL");
+  if (taps_stride < 1) return fail(h, TVOLAP_EINVAL, "taps_stride must be >= 1");
+  int64_t total = 0;
+  for (int c = 0; c < h->C; ++c) total += h->ch_M[c];
+  if (total > INT32_MAX) return fail(h, TVOLAP_EINVAL, "too many partitions");
+  HIP_TRY(h, tvx::launch_irprep_all(h->plan(), h->dtype, h->d_part_base, (int32_t)total, h->d_ch_taps, taps_dev,
+                                    taps_stride, slot, h->d_bank, h->stream));
   return TVOLAP_OK;
 }
 

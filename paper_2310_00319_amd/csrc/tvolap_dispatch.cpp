@@ -75,6 +75,15 @@ hipError_t launch_irprep(const DevPlan& P, int dtype, const float* taps, int32_t
   });
 }
 
+hipError_t launch_irprep_all(const DevPlan& P, int dtype, const int32_t* part_base, int32_t total_parts,
+                             const int32_t* ch_taps, const float* taps, int64_t taps_stride, int32_t slot, void* bank,
+                             hipStream_t s) {
+  return by_hop_dtype(P.L, dtype, [&](auto Lc, auto Dc) {
+    return hop_irprep_all<decltype(Lc)::value, decltype(Dc)::value>(P, dtype, part_base, total_parts, ch_taps, taps,
+                                                                    taps_stride, slot, bank, s);
+  });
+}
+
 hipError_t launch_mac(const DevPlan& P, int dtype, const MacShape& shape, const WorkItem* items, int n_items,
                       const void* bank, const void* fdl, const int32_t* sel, float2* ypart,
                       const uint64_t* counter, hipStream_t s) {

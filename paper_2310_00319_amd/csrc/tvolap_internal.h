@@ -113,6 +113,11 @@ hipError_t launch_batch(const BatchArgs& B, int dtype, const MacShape& shape, in
 hipError_t launch_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M,
                          void* dst, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// One slot of every channel from device taps [C][taps_stride] (part_base:
+// [C+1] prefix sums of the partition counts; ch_taps: [C] taps per channel).
+hipError_t launch_irprep_all(const DevPlan& P, int dtype, const int32_t* part_base, int32_t total_parts,
+                             const int32_t* ch_taps, const float* taps, int64_t taps_stride, int32_t slot, void* bank,
+                             hipStream_t s);
 
 // The same launchers for one hop L and storage type DT, instantiated by the
 // kernel file compiled for that pair; launch_fwd and the others above pick one
@@ -133,6 +138,10 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
 template <int L, int DT>
 hipError_t hop_irprep(const DevPlan& P, int dtype, const float* taps, int32_t n_taps, int32_t M, void* dst,
                       hipStream_t s);
+template <int L, int DT>
+hipError_t hop_irprep_all(const DevPlan& P, int dtype, const int32_t* part_base, int32_t total_parts,
+                          const int32_t* ch_taps, const float* taps, int64_t taps_stride, int32_t slot, void* bank,
+                          hipStream_t s);
 template <int DT>
 hipError_t mac_dt(const DevPlan& P, int dtype, const MacShape& shape, const WorkItem* items, int n_items,
                   const void* bank, const void* fdl, const int32_t* sel, float2* ypart, const uint64_t* counter,

@@ -1199,6 +1199,54 @@ __global__ __launch_bounds__(64) void k_irprep(DevPlan P, const float* __restric
   for (int k = tid; k < N; k += 64) dst[(int64_t)m * N + k] = pack<DT>(fft::real_fwd_post<N>(Z, k, twl));
 }
 
+// Partition spectra of one slot of every channel (eq. 3, 5, 7) in one launch:
+// global partition g (of sum_c M_c, prefix part_base[c]) is channel c's
+// partition m; one partition per wave, 4 waves per workgroup (tables loaded
+// once). Channel c reads taps[c * taps_stride + t] for t < n_taps(c) =
+// min(taps_stride, taps_of_channel[c]); the rest of its partitions are zero.
+template <int L, int DT>
+__global__ __launch_bounds__(256) void k_irprep_all(DevPlan P, const int32_t* __restrict__ part_base,
+                                                    const int32_t* __restrict__ ch_taps, const float* __restrict__ taps,
+                                                    int64_t taps_stride, int32_t slot,
+                                                    typename Store<DT>::T* __restrict__ bank) {
+  constexpr int N = 2 * L;
+  constexpr int W = 4;
+  __shared__ float2 twl[2 * N];
+  __shared__ float winl[N];
+  __shared__ float2 bufA[W][N];
+  __shared__ float2 bufB[W][N];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  load_tables<L, 64 * W>(P, twl, winl, tid);
+  const int total = part_base[P.C];
+  const int gr = blockIdx.x * W + w;
+  const bool live = gr < total;
+  const int g = live ? gr : total - 1;
+  // channel of partition g: the last c with part_base[c] <= g
+  int lo = 0, hi = P.C - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (part_base[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  const int c = lo;
+  const int m = g - part_base[c];
+  const int Mc = P.ch_M[c];
+  const int64_t nt = min((int64_t)ch_taps[c], taps_stride);
+  const float* tc = taps + (int64_t)c * taps_stride;
+  for (int n = lane; n < L; n += 64) {
+    const int64_t t0 = (int64_t)2 * L * m + 2 * n;
+    const float h0 = (t0 < nt) ? tc[t0] : 0.f;
+    const float h1 = (t0 + 1 < nt) ? tc[t0 + 1] : 0.f;
+    bufA[w][n] = make_float2(h0, h1);
+    bufA[w][n + L] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const float2* Z = fft::fft_fwd<N, 64>(bufA[w], bufB[w], twl, lane);
+  if (live) {
+    typename Store<DT>::T* dst = bank + P.ch_bank_off[c] + ((int64_t)slot * Mc + m) * N;
+    for (int k = lane; k < N; k += 64) dst[k] = pack<DT>(fft::real_fwd_post<N>(Z, k, twl));
+  }
+}
+
 __global__ __launch_bounds__(256) void k_fill_zero(uint4* __restrict__ p, size_t n16, uint8_t* __restrict__ tail,
                                                    size_t ntail) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -1372,6 +1420,21 @@ template hipError_t hop_block<TVX_HOP, TVX_DT>(const BlockArgs&, int, const MacS
 template hipError_t hop_batch<TVX_HOP, TVX_DT>(const BatchArgs&, int, const MacShape&, int, const float*, int64_t, float*,
                                        float*, float*, int64_t, hipStream_t, hipEvent_t*);
 template hipError_t hop_irprep<TVX_HOP, TVX_DT>(const DevPlan&, int, const float*, int32_t, int32_t, void*, hipStream_t);
+
+template <int L, int DTT>
+hipError_t hop_irprep_all(const DevPlan& P, int dtype, const int32_t* part_base, int32_t total_parts,
+                          const int32_t* ch_taps, const float* taps, int64_t taps_stride, int32_t slot, void* bank,
+                          hipStream_t s) {
+  if (total_parts <= 0) return hipSuccess;
+  return by_dtype(dtype, [&](auto Dc) {
+    constexpr int DT = decltype(Dc)::value;
+    hipLaunchKernelGGL((k_irprep_all<L, DT>), dim3((total_parts + 3) / 4), dim3(256), 0, s, P, part_base, ch_taps,
+                       taps, taps_stride, slot, static_cast<typename Store<DT>::T*>(bank));
+    return hipGetLastError();
+  });
+}
+template hipError_t hop_irprep_all<TVX_HOP, TVX_DT>(const DevPlan&, int, const int32_t*, int32_t, const int32_t*,
+                                                    const float*, int64_t, int32_t, void*, hipStream_t);
 
 #if TVX_HOP == 64
 template <int DTT>

@@ -87,6 +87,8 @@ def test_null_arguments(lib):
     assert lib.tvolap_create(ctypes.byref(_cfg()), None) == -1
     assert lib.tvolap_destroy(None) == 0
     assert lib.tvolap_process_block(None, None, 0, None, 0, None) == -1
+    assert lib.tvolap_set_irs(None, 0, None, 1) == -1
+    assert lib.tvolap_configure_batch(None, 0, 0, 0, 0, 0) == -1
     assert lib.tvolap_version().decode().startswith("tvolap")
 
 

@@ -256,6 +256,36 @@ def test_full_uneven_workload_sampled_channels():
     _check(wl, channels=chans, name="uneven-full")
 
 
+# ------------------------------------------------------------------ bank loads
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_set_irs_equals_per_channel_set_ir(dtype):
+    """One launch per slot for every channel gives the same bank (bitwise
+    identical output) as one set_ir per channel and slot."""
+    import torch
+    log(f"set_irs {dtype}")
+    seed, L, C, I, N, tr, K, p = SMALL_CASES[4]          # fan-out 4, ragged M
+    wl = synth.random_small(seed=seed + 200, hop=L, n_channels=C, n_inputs=I, n_samples=N,
+                            taps_range=tr, n_slots=K, p_switch=p)
+    ref = gpu_streams(wl, dtype, batch=5)
+    conv = make_convolver(wl, dtype)
+    conv.reset()
+    # overwrite every slot through the one-launch path (rows padded with zeros
+    # plus noise beyond each channel's length, which must be ignored)
+    n = wl.max_taps() + 37
+    rng = np.random.default_rng(3)
+    for s in range(K):
+        rows = rng.standard_normal((C, n)).astype(np.float32)
+        for c in range(C):
+            t = wl.taps[c][s]
+            rows[c, :len(t)] = t
+            rows[c, len(t):int(wl.taps_of_channel[c])] = 0.0
+        conv.set_irs(s, torch.from_numpy(rows).cuda())
+    got = gpu_streams(wl, dtype, conv=conv, batch=5)
+    conv.close()
+    assert np.array_equal(got, ref)
+
+
 # the benchmark's launch configuration: 64-block calls replayed from a HIP graph
 
 def test_full_binaural_bench_configuration():
