@@ -40,6 +40,8 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # 16-bit spectra are multiplied with two-element dot products (4 flop per lane
 # per instruction) accumulating in FP32: twice the FMA rate.
 DOT2_PEAK_TFLOPS = 2 * VALU_PEAK_TFLOPS
+# Dense FP32 matrix-core (MFMA) peak of the chip.
+MFMA_F32_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
     "binaural": dict(desc="64 sources x 2 ears = 128 channels, L=256 (blocks 512, FFT 1024), 96000-tap IRs "
@@ -47,6 +49,8 @@ WORKLOADS = {
                      fn="binaural", dtype="f32"),
     "binaural_bf16": dict(desc="as binaural, IR spectra and delay line stored bf16", fn="binaural", dtype="bf16"),
     "binaural_f16": dict(desc="as binaural, IR spectra and delay line stored f16", fn="binaural", dtype="f16"),
+    "binaural_mix": dict(desc="as binaural, the 128 channels mixed down into the two ear outputs (channel c to ear "
+                              "c mod 2)", fn="binaural", dtype="f32", buses="ear"),
     "binaural_r2": dict(desc="as binaural with hop 128 (blocks 256, FFT 512): the 2-s IRs fall into 375 partitions",
                         fn="binaural", kw=dict(hop=128), dtype="f32"),
     "uneven": dict(desc="512 channels, L=128, IR lengths log-uniform 4800..192000 taps, 2 slots, "
@@ -156,6 +160,36 @@ def cpu_baseline(wl, budget_s: float, keep: list | None = None) -> dict:
                       f"{wl.n_calls}-block stream ({wall:.1f} s wall, {cpu:.1f} s CPU)"}
 
 
+def head_bus_accuracy(wl, buses, got, budget_s: float) -> dict:
+    """Mixdown accuracy: the oracle of every channel over the first blocks of
+    the stream (as many as the budget allows; the outputs up to a block depend
+    only on the input up to it), summed per bus and compared with ``got``."""
+    import dataclasses
+
+    import oracle as orc
+
+    t0 = time.perf_counter()
+    H0 = orc.channel_spectra([t.astype(np.float64) for t in wl.taps[0]], wl.hop, int(wl.taps_of_channel[0]))
+    x0 = wl.padded_input()[0, : 16 * wl.hop].astype(np.float64)
+    orc.tvolap_stream(x0, H0, wl.schedule[:16, 0], wl.hop, 16)
+    per_call = max(1e-6, (time.perf_counter() - t0) / 16)
+    n = int(max(8, min(wl.n_calls, budget_s / (per_call * wl.n_channels))))
+    L = wl.hop
+    head = dataclasses.replace(wl, x=wl.x[:, : n * L], schedule=wl.schedule[:n])
+    x = head.padded_input().astype(np.float64)
+    E = int(np.max(buses)) + 1
+    ref = np.zeros((E, n * L))
+    for c in range(wl.n_channels):
+        H = orc.channel_spectra([t.astype(np.float64) for t in wl.taps[c]], L, int(wl.taps_of_channel[c]))
+        ref[int(buses[c])] += orc.tvolap_stream(x[wl.input_of_channel[c]], H, head.schedule[:, c], L, n)
+    g = got[:, : n * L]
+    rel = np.sqrt(np.sum((g - ref) ** 2, axis=1) / np.maximum(np.sum(ref ** 2, axis=1), 1e-300))
+    snr = -20.0 * np.log10(np.maximum(rel, 1e-30))
+    return {"vs": "FP64 oracle (unquantized), summed per output bus", "buses": E,
+            "blocks_checked": n, "max_rel_rms": float(f"{rel.max():.3e}"),
+            "snr_db": {"min": round(float(snr.min()), 2), "max": round(float(snr.max()), 2)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +213,8 @@ def main():
     ap.add_argument("--bwaves", type=int, default=0, help="batched MAC: waves per workgroup (1, 2 or 4)")
     ap.add_argument("--btb", type=int, default=0, help="batched MAC: blocks per time group (8 or 16)")
     ap.add_argument("--bgroup", type=int, default=0, help="batched MAC: channels per work item (1 or 2)")
+    ap.add_argument("--bengine", type=int, default=0,
+                    help="batched MAC engine: 1 = vector ALU, 2 = matrix cores (f32 spectra)")
     ap.add_argument("--no-ingest", action="store_true", help="skip the IR-bank ingestion timing")
     ap.add_argument("--no-realtime", action="store_true",
                     help="skip the extra one-block-per-call measurement")
@@ -277,9 +313,16 @@ def run(args, spec, wl, stream):
 
     from paper_2310_00319_amd import Convolver
 
+    buses = None
+    mix = {}
+    if spec.get("buses") == "ear":
+        buses = (np.arange(wl.n_channels) % 2).astype(np.int32)
+        mix = dict(n_outputs=2, output_of_channel=buses)
+        if args.mode == "fused":
+            args.mode = "plain"      # a mixdown runs the separate transform-out launch
     conv = Convolver(hop=wl.hop, n_channels=wl.n_channels, max_taps=wl.max_taps(), n_inputs=wl.n_inputs,
                      input_of_channel=wl.input_of_channel, taps_of_channel=wl.taps_of_channel,
-                     n_slots=wl.n_slots, dtype=spec["dtype"], stream=stream, max_batch=max(16, args.batch))
+                     n_slots=wl.n_slots, dtype=spec["dtype"], stream=stream, max_batch=max(16, args.batch), **mix)
     t0 = time.perf_counter()
     for c in range(wl.n_channels):
         for s in range(wl.n_slots):
@@ -318,14 +361,14 @@ def run(args, spec, wl, stream):
         del rows
     tuned_us = None
     tuned_batch_us = None
-    if args.batch > 1 and (args.bchunk or args.bvec or args.bwaves or args.btb or args.bgroup):
+    if args.batch > 1 and (args.bchunk or args.bvec or args.bwaves or args.btb or args.bgroup or args.bengine):
         conv.configure_batch(chunk=args.bchunk, vec=args.bvec, waves=args.bwaves, time_block=args.btb,
-                             group=args.bgroup)
+                             group=args.bgroup, engine=args.bengine)
     elif args.batch > 1 and not args.no_autotune:
         t0 = time.perf_counter()
         tuned_batch_us = conv.autotune_batch(iters=3)
         log(f"batched schedule autotuned in {time.perf_counter() - t0:.2f} s: best {tuned_batch_us:.2f} us/block")
-    if args.mode != "fused" or args.chunk or args.waves or args.grid or args.no_autotune:
+    if (args.mode != "fused" and buses is None) or args.chunk or args.waves or args.grid or args.no_autotune:
         conv.configure(fused={"fused": 1, "two": 2, "plain": 0}[args.mode], chunk=args.chunk, waves=args.waves,
                        grid=args.grid)
     else:
@@ -337,7 +380,7 @@ def run(args, spec, wl, stream):
 
     x = torch.from_numpy(wl.padded_input()).cuda()
     sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
-    out = torch.empty((wl.n_channels, wl.n_calls * wl.hop), device="cuda", dtype=torch.float32)
+    out = torch.empty((conv.n_outputs, wl.n_calls * wl.hop), device="cuda", dtype=torch.float32)
     torch.cuda.synchronize()
 
     if args.graph:
@@ -437,25 +480,31 @@ def run(args, spec, wl, stream):
         gbs = kbytes / (mac_ms * 1e-3) / 1e9
         tfs = kflops / (mac_ms * 1e-3) / 1e12
         floor_hbm = kbytes / (HBM_PEAK_GBS * 1e9)
-        alu_peak = VALU_PEAK_TFLOPS if spec["dtype"] == "f32" else DOT2_PEAK_TFLOPS
+        mfma = info["batch_engine"] == 2
+        kname = "k_tmfma" if mfma else "k_tmac"
+        alu_peak = (MFMA_F32_PEAK_TFLOPS if mfma else VALU_PEAK_TFLOPS) if spec["dtype"] == "f32" \
+            else DOT2_PEAK_TFLOPS
         floor_alu = kflops / (alu_peak * 1e12)
         per_block = info["mac_bytes_per_block"] * wl.n_calls / calls_per_step
-        tr = measured_traffic(f"{args.workload} batch{args.batch} k_tmac")
+        tr = measured_traffic(f"{args.workload} batch{args.batch} {kname}")
         hbm = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                "bytes_per_launch": int(kbytes), "floor_us": round(floor_hbm * 1e6, 2)}
         alu = {"achieved": round(tfs, 2), "peak": round(alu_peak, 2), "unit": "TFLOP/s",
                "frac": round(tfs / alu_peak, 4), "flops_per_launch": int(kflops),
                "floor_us": round(floor_alu * 1e6, 2),
-               "peak_note": ("FP32 FMA issue rate without packed-FP32 instructions (256 CU x 4 SIMD x 16 lanes x "
+               "peak_note": ("dense FP32 matrix-core peak (4x4x1 MFMAs, 16 bins each)" if mfma else
+                             "FP32 FMA issue rate without packed-FP32 instructions (256 CU x 4 SIMD x 16 lanes x "
                              "2 flop x 2.4 GHz); the published packed figure is 157.3") if spec["dtype"] == "f32"
                else ("two-element 16-bit dot products with FP32 accumulation: 256 CU x 4 SIMD x 16 lanes x "
                      "4 flop x 2.4 GHz")}
-        main, other = (("hbm", hbm), ("alu", alu)) if floor_hbm >= floor_alu else (("alu", alu), ("hbm", hbm))
+        cname = "mfma" if mfma else "alu"
+        main, other = (("hbm", hbm), (cname, alu)) if floor_hbm >= floor_alu else ((cname, alu), ("hbm", hbm))
         roof = {"bound": main[0], "achieved": main[1]["achieved"], "peak": main[1]["peak"], "unit": main[1]["unit"],
                 "frac": main[1]["frac"], "traffic": tr[0] if tr else None,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "traffic_source": tr[1] if tr else None,
-                "kernel": "k_tmac (time-blocked spectral MAC of eq. 8 over a batch of blocks)",
+                "kernel": (("k_tmfma (time-blocked spectral MAC of eq. 8 on matrix cores)" if mfma else
+                            "k_tmac (time-blocked spectral MAC of eq. 8 over a batch of blocks)")),
                 "avg_launch_us": round(mac_ms * 1e3, 3), main[0]: main[1], other[0]: other[1],
                 "bytes_note": "unique delay-line and partition spectra of each call",
                 "per_block_bytes_per_launch": int(per_block),
@@ -495,14 +544,17 @@ def run(args, spec, wl, stream):
         conv.reset()
         conv.process(x, sched, out, batch=args.batch)
         torch.cuda.synchronize()
-        got = out[: len(ref)].double().cpu().numpy()
-        ref = np.stack(ref)
-        rel = np.sqrt(np.sum((got - ref) ** 2, axis=1) / np.maximum(np.sum(ref ** 2, axis=1), 1e-300))
-        snr = -20.0 * np.log10(np.maximum(rel, 1e-30))
-        accuracy = {"vs": "FP64 oracle (unquantized)", "channels": int(len(ref)),
-                    "max_rel_rms": float(f"{rel.max():.3e}"),
-                    "snr_db": {"min": round(float(snr.min()), 2), "median": round(float(np.median(snr)), 2),
-                               "max": round(float(snr.max()), 2)}}
+        if buses is not None:
+            accuracy = head_bus_accuracy(wl, buses, out.double().cpu().numpy(), args.cpu_budget)
+        else:
+            got = out[: len(ref)].double().cpu().numpy()
+            ref = np.stack(ref)
+            rel = np.sqrt(np.sum((got - ref) ** 2, axis=1) / np.maximum(np.sum(ref ** 2, axis=1), 1e-300))
+            snr = -20.0 * np.log10(np.maximum(rel, 1e-30))
+            accuracy = {"vs": "FP64 oracle (unquantized)", "channels": int(len(ref)),
+                        "max_rel_rms": float(f"{rel.max():.3e}"),
+                        "snr_db": {"min": round(float(snr.min()), 2), "median": round(float(np.median(snr)), 2),
+                                   "max": round(float(snr.max()), 2)}}
         log(f"accuracy: {accuracy}")
 
     res = {
@@ -521,7 +573,7 @@ def run(args, spec, wl, stream):
         "config": {"workload": f"{args.workload}: {spec['desc']}", "channels": wl.n_channels,
                    "inputs": wl.n_inputs, "hop": wl.hop, "ir_taps": int(wl.max_taps()),
                    "partitions_total": info["sum_partitions"], "blocks_per_step": blocks,
-                   "spectra_dtype": spec["dtype"]},
+                   "spectra_dtype": spec["dtype"], "outputs": conv.n_outputs},
         "us_per_block": round(us_per_block, 3),
         "real_time_factor": round(rtf, 1),
         "roofline": roof,
@@ -537,6 +589,7 @@ def run(args, spec, wl, stream):
                      "autotuned_us_per_block": tuned_us,
                      "batch": {"chunk": info["batch_chunk"], "vec": info["batch_vec"], "waves": info["batch_waves"],
                                "time_block": info["batch_time_block"], "group": info["batch_group"],
+                               "engine": {1: "vector ALU", 2: "matrix cores"}[info["batch_engine"]],
                                "tile_width": info["batch_tile_width"], "work_items": info["batch_work_items"],
                                "autotuned_us_per_block": tuned_batch_us}},
     }

@@ -67,6 +67,14 @@ typedef struct {
   int32_t max_batch;                /* largest n_blocks of tvolap_process_blocks, 0..1024
                                        (0 = 16). The delay line keeps (max_batch-1)/2
                                        extra spectra per parity.                         */
+  int32_t n_outputs;                /* 0: one output per channel. E > 0: a mixdown into E
+                                       output buses: the outputs of the parallel
+                                       channels (end of Sec. 2) summed per bus.          */
+  const int32_t* output_of_channel; /* host [C] bus of each channel (every bus gets at
+                                       least one channel); used when n_outputs > 0. The
+                                       channels' spectra are summed per bus before one
+                                       inverse transform (the transforms are linear).
+                                       A mixdown runs the per-block path with fused = 0. */
 } tvolap_config;
 
 /* Sizes of a handle, for accounting. Bytes count what one processed block must
@@ -98,6 +106,8 @@ typedef struct {
   int32_t batch_rows;               /* partial-spectrum rows per block                   */
   int32_t batch_time_block;         /* blocks of one parity per time group (8 or 16)     */
   int32_t batch_group;              /* channels of one input per work item (1 or 2)      */
+  int32_t batch_engine;             /* 1 = vector ALU, 2 = matrix cores                  */
+  int32_t n_outputs;                /* output rows: n_channels, or the mixdown buses     */
 } tvolap_info;
 
 /* Create a convolver (Sec. 2: partitioned, block-synchronously switchable,
@@ -146,7 +156,8 @@ int tvolap_select_ir(tvolap_t* h, const int32_t* slot_of_channel);
 
 /* Process one block (Sec. 2, eq. 1-13; Fig. 2). `in` is a device array holding
  * L new samples of every input, input i at in[i*in_stride + n], n < L; `out`
- * receives L samples of every channel at out[c*out_stride + n]. Strides are in
+ * receives L samples of every output (channel, or bus with a mixdown) at
+ * out[c*out_stride + n]. Strides are in
  * floats, >= L. Call number c (counting from creation or the last reset)
  * consumes input samples [cL, (c+1)L), completes input block c - 1 (covering
  * [(c-1)L, (c+1)L)) and emits output samples [(c-1)L, cL): the stream is the
@@ -220,14 +231,19 @@ int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us);
  * (0 = 4, fewer when 2L bins are fewer); time_block: 8 or 16 (16 needs vec 1;
  * 0 = 16 when max_batch >= 32, else 8); group: channels of one input per work
  * item, 1 or 2 (two channels share the delay-line loads; 0 = 2 when an input
- * feeds several channels). Waits for the stream; rebuilds the batched work
- * list. Errors: EINVAL, ESTATE during capture, ENOMEM/EDEVICE. */
+ * feeds several channels); engine: 1 = vector ALU (multiply-adds or packed
+ * dot products per complex product), 2 = matrix cores (f32 spectra only: per
+ * bin, the products of a time group of 16 blocks and the two channels of an
+ * input are 4x4 outer products, one 16-bin MFMA each; needs time groups of 16
+ * and vec 1, which it implies), 0 = 1. Waits for the stream; rebuilds the
+ * batched work list. Errors: EINVAL (also engine 2 with 16-bit spectra),
+ * ESTATE during capture, ENOMEM/EDEVICE. */
 int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block,
-                           int32_t group);
+                           int32_t group, int32_t engine);
 
 /* Autotuner for batched calls: times `iters` calls of max_batch blocks (zero
  * input, current bank, block b of the batch in slot b mod K) for each
- * candidate (group, time_block, vec, waves, chunk), keeps the fastest, caches it for handles of
+ * candidate (engine, group, time_block, vec, waves, chunk), keeps the fastest, caches it for handles of
  * the same shape and max_batch in this process, then resets the stream state
  * as tvolap_reset does. *best_us (may be NULL) receives the best time per
  * block in microseconds, or -1 when the choice came from the cache.

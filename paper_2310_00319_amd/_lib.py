@@ -58,6 +58,8 @@ class TvolapConfig(ctypes.Structure):
         ("spectra_dtype", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("max_batch", ctypes.c_int32),
+        ("n_outputs", ctypes.c_int32),
+        ("output_of_channel", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -87,6 +89,8 @@ class TvolapInfo(ctypes.Structure):
         ("batch_rows", ctypes.c_int32),
         ("batch_time_block", ctypes.c_int32),
         ("batch_group", ctypes.c_int32),
+        ("batch_engine", ctypes.c_int32),
+        ("n_outputs", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -134,7 +138,7 @@ def _declare(lib):
     lib.tvolap_last_error.restype = ctypes.c_char_p
     lib.tvolap_configure.argtypes = [c_vp, c_i32, c_i32, c_i32, c_i32]
     lib.tvolap_autotune.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_float)]
-    lib.tvolap_configure_batch.argtypes = [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32]
+    lib.tvolap_configure_batch.argtypes = [c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32]
     lib.tvolap_autotune_batch.argtypes = [c_vp, c_i32, ctypes.POINTER(ctypes.c_float)]
     lib.tvolap_capture_begin.argtypes = [c_vp]
     lib.tvolap_capture_end.argtypes = [c_vp]

@@ -32,11 +32,14 @@ class Convolver:
     n_slots           K IR slots per channel.
     dtype             storage of IR spectra and delay line: "f32", "bf16", "f16".
     max_batch         largest number of blocks per batched call (process(..., batch=n)).
+    n_outputs         0: one output row per channel; E > 0: a mixdown into E buses.
+    output_of_channel [C] bus of each channel (with n_outputs > 0).
     """
 
     def __init__(self, hop: int, n_channels: int, max_taps: int, n_inputs: int | None = None,
                  input_of_channel=None, taps_of_channel=None, n_slots: int = 1, dtype: str = "f32",
-                 device=None, stream: torch.cuda.Stream | None = None, max_batch: int = 16):
+                 device=None, stream: torch.cuda.Stream | None = None, max_batch: int = 16,
+                 n_outputs: int = 0, output_of_channel=None):
         self._lib = load()
         self._h = ctypes.c_void_p()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
@@ -47,6 +50,7 @@ class Convolver:
         self.n_slots = int(n_slots)
         self.dtype = dtype
         self.max_batch = int(max_batch)
+        self.n_outputs = int(n_outputs) if n_outputs else self.n_channels
         if dtype not in DTYPES:
             raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
         with torch.cuda.device(self.device):
@@ -69,6 +73,13 @@ class Convolver:
             cfg.spectra_dtype = DTYPES[dtype]
             cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
             cfg.max_batch = self.max_batch
+            if n_outputs:
+                if output_of_channel is None:
+                    raise ValueError("output_of_channel is required with n_outputs")
+                o = _i32_host(output_of_channel, self.n_channels, "output_of_channel")
+                self._keep.append(o)
+                cfg.n_outputs = int(n_outputs)
+                cfg.output_of_channel = o.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
             check(self._lib.tvolap_create(ctypes.byref(cfg), ctypes.byref(self._h)), None)
             self._keep = []
 
@@ -128,11 +139,11 @@ class Convolver:
 
     def process_block(self, x: torch.Tensor, out: torch.Tensor | None = None,
                       slots: torch.Tensor | None = None) -> torch.Tensor:
-        """One block: x [I][>=L] (first L samples used) -> out [C][>=L]."""
+        """One block: x [I][>=L] (first L samples used) -> out [E][>=L] (E = C without a mixdown)."""
         self._check_2d(x, self.n_inputs, "x")
         if out is None:
-            out = torch.empty((self.n_channels, self.hop), device=x.device, dtype=torch.float32)
-        self._check_2d(out, self.n_channels, "out")
+            out = torch.empty((self.n_outputs, self.hop), device=x.device, dtype=torch.float32)
+        self._check_2d(out, self.n_outputs, "out")
         sp = None
         if slots is not None:
             if not slots.is_cuda or slots.dtype != torch.int32 or slots.numel() != self.n_channels \
@@ -145,7 +156,7 @@ class Convolver:
 
     def process(self, x: torch.Tensor, schedule: torch.Tensor | None = None,
                 out: torch.Tensor | None = None, batch: int = 1) -> torch.Tensor:
-        """Stream a resident signal: x [I][n*L] -> out [C][n*L]; schedule
+        """Stream a resident signal: x [I][n*L] -> out [E][n*L]; schedule
         [n][C] int32 (device) gives the slots of every block. batch = 1: one
         process_block per L samples; batch > 1: process_blocks over up to
         `batch` blocks at a time (same results)."""
@@ -153,8 +164,8 @@ class Convolver:
         self._check_2d(x, self.n_inputs, "x")
         n = x.shape[1] // L
         if out is None:
-            out = torch.empty((self.n_channels, n * L), device=x.device, dtype=torch.float32)
-        self._check_2d(out, self.n_channels, "out")
+            out = torch.empty((self.n_outputs, n * L), device=x.device, dtype=torch.float32)
+        self._check_2d(out, self.n_outputs, "out")
         if out.shape[1] < n * L:
             raise ValueError("out too short")
         if schedule is not None:
@@ -193,10 +204,12 @@ class Convolver:
         check(self._lib.tvolap_autotune(self._h, int(iters), ctypes.byref(best)), self._h)
         return best.value
 
-    def configure_batch(self, chunk: int = 0, vec: int = 0, waves: int = 0, time_block: int = 0, group: int = 0):
-        """Schedule of batched calls (process with batch > 1)."""
+    def configure_batch(self, chunk: int = 0, vec: int = 0, waves: int = 0, time_block: int = 0, group: int = 0,
+                        engine: int = 0):
+        """Schedule of batched calls (process with batch > 1); engine 1 = vector
+        ALU, 2 = matrix cores (f32 spectra), 0 = 1."""
         check(self._lib.tvolap_configure_batch(self._h, int(chunk), int(vec), int(waves), int(time_block),
-                                               int(group)), self._h)
+                                               int(group), int(engine)), self._h)
 
     def autotune_batch(self, iters: int = 5) -> float:
         best = ctypes.c_float()

@@ -44,11 +44,11 @@ struct MacChoice {
   int32_t chunk = 0, waves = 4, grid = 0, fused = 1, vec = 4;
 };
 
-// Schedule of the time-blocked MAC of batched calls: partitions per item
-// (0 = automatic), complex bins per lane (0 = automatic), waves per tile
-// (0 = automatic).
+// Schedule of the time-blocked MAC of batched calls: partitions per item,
+// complex bins per lane, waves per tile, blocks per time group, channels per
+// item (0 = automatic for each) and engine (1 = vector ALU, 2 = matrix cores).
 struct BatchChoice {
-  int32_t chunk = 0, vec = 0, waves = 0, time_block = 0, group = 0;
+  int32_t chunk = 0, vec = 0, waves = 0, time_block = 0, group = 0, engine = 0;
 };
 
 // Autotuner results, keyed by the handle's shape (hop, channels, inputs,
@@ -77,7 +77,12 @@ struct tvolap {
   void* d_bank = nullptr;
   void* d_fdl = nullptr;
   float* d_hist = nullptr;      // [2][I][L]
-  float* d_ola = nullptr;       // [C][3L]
+  float* d_ola = nullptr;       // [n_out][3L]
+  int32_t n_out = 0;            // output buses (C without a mixdown)
+  bool mixdown = false;
+  std::vector<int32_t> out_ptr, out_ch;   // bus e: channels out_ch[out_ptr[e] .. out_ptr[e+1])
+  int32_t* d_out_ptr = nullptr;
+  int32_t* d_out_ch = nullptr;
   int32_t* d_sel = nullptr;     // [C]
   uint64_t* d_counter = nullptr;
   float2* d_tw = nullptr;       // [4L]
@@ -155,6 +160,7 @@ struct tvolap {
     P.in_M = d_in_M; P.in_fdl_off = d_in_fdl_off; P.tw = d_tw; P.win = d_win;
     P.ch_row_base = d_ch_row_base; P.ch_nchunks = d_ch_nchunks; P.tile_width = tile_width;
     P.in_ch_ptr = d_in_ch_ptr; P.in_ch = d_in_ch;
+    P.n_out = n_out; P.out_ptr = d_out_ptr; P.out_ch = d_out_ch;
     return P;
   }
 };
@@ -219,6 +225,7 @@ void free_all(tvolap_t* h) {
   free_work(h);
   free_batch_work(h);
   dfree(h->d_bank); dfree(h->d_fdl); dfree(h->d_hist); dfree(h->d_ola); dfree(h->d_sel);
+  dfree(h->d_out_ptr); dfree(h->d_out_ch);
   dfree(h->d_counter); dfree(h->d_tw); dfree(h->d_win); dfree(h->d_ch_input); dfree(h->d_ch_M);
   dfree(h->d_ch_bank_off); dfree(h->d_in_M); dfree(h->d_in_fdl_off); dfree(h->d_taps);
   dfree(h->d_arrive); dfree(h->d_done); dfree(h->d_zero_in); dfree(h->d_tune_out); dfree(h->d_tune_sel);
@@ -336,7 +343,8 @@ void build_work(tvolap_t* h, int S_req, int waves, int vec) {
 }
 
 // Work list of the time-blocked MAC (batched calls): channels grouped by
-// input (up to 2 per item), the 2L bins cut into tiles of 64 V NW, each
+// input (up to 2 per item), the 2L bins cut into tiles of 64 V NW (16 NW for
+// the matrix-core engine), each
 // group's partitions [0, M) cut into chunks of S. The partial rows of a
 // channel are contiguous in (tile, chunk) order. Each item runs once per
 // time group (a parity class of up to b_tb (8 or 16) blocks of the call).
@@ -345,6 +353,9 @@ void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   // time groups of 16 blocks (one bin per lane) when calls can hold 32 blocks
   int V = (bc.vec == 1) ? 1 : 2;
   int TB = bc.time_block == 16 ? 16 : (bc.time_block == 8 ? 8 : (h->max_batch >= 32 ? 16 : 8));
+  const int engine = (bc.engine == 2 && h->dtype == 0) ? 2 : 1;
+  if (engine == 2) { TB = 16; V = 1; }   // matrix cores: time groups of 16, 64 bins per wave
+  h->bshape.E = engine == 2 ? 1 : 0;
   if (TB == 16 && bc.vec == 0) V = 1;
   if (TB == 16 && V != 1) TB = 8;
   h->b_tb = TB;
@@ -354,7 +365,7 @@ void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   while (64 * V * NW > N && NW > 1) NW /= 2;
   h->bshape.V = V;
   h->bshape.NW = NW;
-  h->b_tile_width = 64 * V * NW;
+  h->b_tile_width = (engine == 2 ? 16 : 64 * V) * NW;   // matrix cores: 16 bins per wave
   const int T = N / h->b_tile_width;
 
   std::vector<std::vector<int>> by_input(h->I);
@@ -463,6 +474,7 @@ int apply_batch_choice(tvolap_t* h, const BatchChoice& c) {
   h->bchoice.waves = h->bshape.NW;
   h->bchoice.time_block = h->b_tb;
   h->bchoice.group = h->bshape.G;
+  h->bchoice.engine = h->bshape.E == 1 ? 2 : 1;
   return TVOLAP_OK;
 }
 
@@ -510,6 +522,16 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   }
   h->max_batch = cfg->max_batch > 0 ? cfg->max_batch : 16;
   h->ring_extra = (h->max_batch - 1) / 2;
+  // output buses
+  h->mixdown = cfg->n_outputs > 0;
+  h->n_out = h->mixdown ? cfg->n_outputs : h->C;
+  h->out_ptr.assign(h->n_out + 1, 0);
+  h->out_ch.clear();
+  for (int e = 0; e < h->n_out; ++e) {
+    for (int c = 0; c < h->C; ++c)
+      if ((h->mixdown ? cfg->output_of_channel[c] : c) == e) h->out_ch.push_back(c);
+    h->out_ptr[e + 1] = (int32_t)h->out_ch.size();
+  }
   h->in_Mdata.assign(h->I, 1);
   for (int c = 0; c < h->C; ++c)
     h->in_Mdata[h->ch_input[c]] = std::max(h->in_Mdata[h->ch_input[c]], h->ch_M[c]);
@@ -533,7 +555,11 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_bank, (size_t)h->bank_elems * h->store_bytes));
   HIP_TRY(h, dalloc(&h->d_fdl, (size_t)h->fdl_elems * h->store_bytes));
   HIP_TRY(h, dalloc(&h->d_hist, (size_t)2 * h->I * L * sizeof(float)));
-  HIP_TRY(h, dalloc(&h->d_ola, (size_t)h->C * 3 * L * sizeof(float)));
+  HIP_TRY(h, dalloc(&h->d_ola, (size_t)h->n_out * 3 * L * sizeof(float)));
+  HIP_TRY(h, dalloc(&h->d_out_ptr, (size_t)(h->n_out + 1) * sizeof(int32_t)));
+  HIP_TRY(h, dalloc(&h->d_out_ch, (size_t)h->C * sizeof(int32_t)));
+  HIP_TRY(h, hipMemcpy(h->d_out_ptr, h->out_ptr.data(), (h->n_out + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(h->d_out_ch, h->out_ch.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(h, dalloc(&h->d_sel, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_counter, sizeof(uint64_t)));
   HIP_TRY(h, dalloc(&h->d_tw, (size_t)4 * L * sizeof(float2)));
@@ -597,7 +623,7 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   HIP_TRY(h, hipMemsetAsync(h->d_bank, 0, (size_t)h->bank_elems * h->store_bytes, h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_fdl, 0, (size_t)h->fdl_elems * h->store_bytes, h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_hist, 0, (size_t)2 * h->I * L * sizeof(float), h->stream));
-  HIP_TRY(h, hipMemsetAsync(h->d_ola, 0, (size_t)h->C * 3 * L * sizeof(float), h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->d_ola, 0, (size_t)h->n_out * 3 * L * sizeof(float), h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_sel, 0, (size_t)h->C * sizeof(int32_t), h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_counter, 0, sizeof(uint64_t), h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_arrive, 0, (size_t)h->C * sizeof(int32_t), h->stream));
@@ -610,6 +636,7 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   h->sel_ev_made = true;
 
   MacChoice c;
+  if (h->mixdown) c.fused = 0;   // bus sums run in the separate transform-out launch
   RC_TRY(apply_choice(h, c));
   RC_TRY(apply_batch_choice(h, BatchChoice{}));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -707,7 +734,7 @@ int enqueue_block(tvolap_t* h, const float* in, int64_t in_stride, float* out, i
 int reset_state(tvolap_t* h) {
   HIP_TRY(h, tvx::launch_fill_zero(h->d_fdl, (size_t)h->fdl_elems * h->store_bytes, h->stream));
   HIP_TRY(h, tvx::launch_fill_zero(h->d_hist, (size_t)2 * h->I * h->L * sizeof(float), h->stream));
-  HIP_TRY(h, tvx::launch_fill_zero(h->d_ola, (size_t)h->C * 3 * h->L * sizeof(float), h->stream));
+  HIP_TRY(h, tvx::launch_fill_zero(h->d_ola, (size_t)h->n_out * 3 * h->L * sizeof(float), h->stream));
   HIP_TRY(h, tvx::launch_fill_zero(h->d_counter, sizeof(uint64_t), h->stream));
   HIP_TRY(h, tvx::launch_fill_zero(h->d_arrive, (size_t)h->C * sizeof(int32_t), h->stream));
   HIP_TRY(h, tvx::launch_fill_zero(h->d_done, sizeof(int32_t), h->stream));
@@ -746,6 +773,19 @@ int tvolap_create(const tvolap_config* cfg, tvolap_t** out) {
     return fail(nullptr, TVOLAP_EINVAL, "max_batch must be in [0, 1024]");
   if (!cfg->input_of_channel && cfg->n_inputs != cfg->n_channels)
     return fail(nullptr, TVOLAP_EINVAL, "input_of_channel is NULL but n_inputs != n_channels");
+  if (cfg->n_outputs < 0 || cfg->n_outputs > cfg->n_channels)
+    return fail(nullptr, TVOLAP_EINVAL, "n_outputs must be in [0, n_channels]");
+  if (cfg->n_outputs > 0) {
+    if (!cfg->output_of_channel) return fail(nullptr, TVOLAP_EINVAL, "output_of_channel is NULL");
+    std::vector<int> used(cfg->n_outputs, 0);
+    for (int c = 0; c < cfg->n_channels; ++c) {
+      const int e = cfg->output_of_channel[c];
+      if (e < 0 || e >= cfg->n_outputs) return fail(nullptr, TVOLAP_EINVAL, "output_of_channel value out of range");
+      used[e] = 1;
+    }
+    for (int e = 0; e < cfg->n_outputs; ++e)
+      if (!used[e]) return fail(nullptr, TVOLAP_EINVAL, "every output needs at least one channel");
+  }
   for (int c = 0; c < cfg->n_channels; ++c) {
     if (cfg->input_of_channel &&
         (cfg->input_of_channel[c] < 0 || cfg->input_of_channel[c] >= cfg->n_inputs))
@@ -862,7 +902,7 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   if (n_blocks < 1 || n_blocks > h->max_batch) return fail(h, TVOLAP_EINVAL, "n_blocks outside [1, max_batch]");
   if (in_stride < (int64_t)n_blocks * h->L && h->I > 1)
     return fail(h, TVOLAP_EINVAL, "in_stride smaller than n_blocks * hop");
-  if (out_stride < (int64_t)n_blocks * h->L && h->C > 1)
+  if (out_stride < (int64_t)n_blocks * h->L && h->n_out > 1)
     return fail(h, TVOLAP_EINVAL, "out_stride smaller than n_blocks * hop");
   if (slots_dev && slots_stride < h->C) return fail(h, TVOLAP_EINVAL, "slots_stride smaller than n_channels");
   BatchArgs B;
@@ -887,6 +927,7 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   B.arrive = h->d_arrive;
   B.done = h->d_done;
   B.counter = h->d_counter;
+  B.bus_rows = h->mixdown ? 1 : 0;
   const int groups = ((n_blocks + 1) / 2 + h->b_tb - 1) / h->b_tb;
   const int grid = 8 * ((2 * h->n_bmac + 7) / 8) * groups;   // k_tmac's XCD-aware index space
   TimingSet* ts = nullptr;
@@ -914,6 +955,7 @@ int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, i
   if (chunk < 0 || grid < 0) return fail(h, TVOLAP_EINVAL, "chunk and grid must be >= 0");
   if (waves != 0 && waves != 4 && waves != 8) return fail(h, TVOLAP_EINVAL, "waves must be 0, 4 or 8");
   if (fused < 0 || fused > 2) return fail(h, TVOLAP_EINVAL, "fused must be 0, 1 or 2");
+  if (h->mixdown && fused != 0) return fail(h, TVOLAP_EINVAL, "a mixdown runs with fused = 0");
   MacChoice c;
   c.fused = fused;
   c.chunk = chunk;
@@ -923,7 +965,7 @@ int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, i
 }
 
 int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block,
-                           int32_t group) {
+                           int32_t group, int32_t engine) {
   if (!h) return TVOLAP_EINVAL;
   if (h->capturing) return fail(h, TVOLAP_ESTATE, "cannot reconfigure during graph capture");
   if (chunk < 0) return fail(h, TVOLAP_EINVAL, "chunk must be >= 0");
@@ -933,7 +975,12 @@ int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t wave
     return fail(h, TVOLAP_EINVAL, "time_block must be 0, 8 or 16");
   if (time_block == 16 && vec == 2) return fail(h, TVOLAP_EINVAL, "time_block 16 needs vec 1");
   if (group != 0 && group != 1 && group != 2) return fail(h, TVOLAP_EINVAL, "group must be 0, 1 or 2");
+  if (engine < 0 || engine > 2) return fail(h, TVOLAP_EINVAL, "engine must be 0, 1 or 2");
+  if (engine == 2 && h->dtype != 0) return fail(h, TVOLAP_EINVAL, "the matrix-core engine needs f32 spectra");
+  if (engine == 2 && (vec == 2 || time_block == 8))
+    return fail(h, TVOLAP_EINVAL, "the matrix-core engine runs vec 1 and time groups of 16");
   BatchChoice c;
+  c.engine = engine;
   c.chunk = chunk;
   c.vec = vec;
   c.waves = waves;
@@ -997,14 +1044,19 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
   }
   std::vector<int> groups = {fan >= 2 ? 2 : 1};
   if (fan >= 2) groups.push_back(1);
+  std::vector<int> engines = {1};
+  if (h->dtype == 0) engines.push_back(2);
+  for (int eng : engines)
   for (int grp : groups)
   for (int tb : tbs)
   for (int vec : vecs) {
     if (tb == 16 && vec != 1) continue;
+    if (eng == 2 && (tb != 16 || vec != 1)) continue;
     const int tgroups = 2 * (((nb + 1) / 2 + tb - 1) / tb);
     for (int nw : {1, 2, 4}) {
-      if (64 * vec * nw > N) continue;
-      const int tiles = N / (64 * vec * nw);
+      const int tw = (eng == 2 ? 16 : 64 * vec) * nw;
+      if (tw > N) continue;
+      const int tiles = N / tw;
       std::vector<int> chunks;
       for (int half_per_cu : {1, 2, 4, 8, 16}) {
         const int64_t target = (int64_t)half_per_cu * h->n_cu / 2;
@@ -1019,6 +1071,7 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
         c.waves = nw;
         c.time_block = tb;
         c.group = grp;
+        c.engine = eng;
         rc = apply_batch_choice(h, c);
         if (rc != TVOLAP_OK) break;
         // every block of the batch selects slot (block mod K), as a switching stream does
@@ -1100,8 +1153,9 @@ int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us) {
   float best_t = 1e30f;
   int rc = TVOLAP_OK;
   const std::vector<int> vecs = h->dtype == 0 ? std::vector<int>{2} : std::vector<int>{2, 4};
+  const std::vector<int> modes = h->mixdown ? std::vector<int>{0} : std::vector<int>{1, 2};
   for (int vec : vecs)
-  for (int mode : {1, 2})
+  for (int mode : modes)
   for (int S : chunks) {
     for (int nw : {4, 8}) {
       for (int gmul : {0, 1, 2, 4}) {
@@ -1223,6 +1277,7 @@ int tvolap_get_info(const tvolap_t* h, tvolap_info* info) {
   info->mac_waves = h->shape.NW;
   info->mac_grid = grid_of(h);
   info->fused = h->choice.fused;
+  info->n_outputs = h->n_out;
   info->batch_chunk = h->b_chunk;
   info->batch_vec = h->bshape.V;
   info->batch_waves = h->bshape.NW;
@@ -1231,6 +1286,7 @@ int tvolap_get_info(const tvolap_t* h, tvolap_info* info) {
   info->batch_rows = h->n_brows;
   info->batch_time_block = h->b_tb;
   info->batch_group = h->bshape.G;
+  info->batch_engine = h->bshape.E == 1 ? 2 : 1;
   info->n_cu = h->n_cu;
   return TVOLAP_OK;
 }

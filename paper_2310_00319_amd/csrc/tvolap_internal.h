@@ -24,6 +24,11 @@ struct DevPlan {
   const int32_t* in_ch_ptr;    // [I+1] channels of input i: in_ch[in_ch_ptr[i] .. in_ch_ptr[i+1])
   const int32_t* in_ch;        // [C]
   int32_t tile_width;          // bins per MAC tile (64 V)
+  // Output buses: bus e is the sum of channels out_ch[out_ptr[e] .. out_ptr[e+1])
+  // (without a mixdown, bus c is channel c alone).
+  int32_t n_out;
+  const int32_t* out_ptr;      // [n_out+1]
+  const int32_t* out_ch;       // [C]
 };
 
 // One unit of per-block work. kind 1: the new spectrum of input `input`.
@@ -67,6 +72,7 @@ struct MacShape {
   int32_t V;    // complex bins per lane (tile width = 64 V)
   int32_t G;    // channel capacity of a work item (1, 2 or 4)
   int32_t NW;   // waves per workgroup (split the partition range)
+  int32_t E = 0;  // batched MAC engine: 0 = vector ALU (k_tmac), 1 = matrix cores (k_tmfma)
 };
 
 // Launchers (tvolap_kernels.hip). dtype: 0 = f32, 1 = bf16, 2 = f16.
@@ -101,9 +107,10 @@ struct BatchArgs {
   float2* ypart;               // [n_max][rows][tile_width]
   float* yblk;                 // [n_max][C][4L]
   float* ola_state;            // [C][3L]
-  int32_t* arrive;             // [C] overlap-add workgroups finished per channel (zero between calls)
+  int32_t* arrive;             // [C] overlap-add workgroups finished per output (zero between calls)
   int32_t* done;
   uint64_t* counter;
+  int32_t bus_rows;            // 1: mixdown; bus sums are formed in the partial rows before the inverse
 };
 // ev (may be NULL): four events recorded before the spectra, before the MAC,
 // after the MAC and after the overlap-add.

@@ -340,7 +340,7 @@ __device__ __forceinline__ void inverse_ola(float2* Y, float2* bufA, float2* buf
 // tiles (partitions m >= 1) plus H_{c, slot}(0) X(l) (eq. 8, m = 0 term, X(l)
 // read back from the delay line). COHERENT: the partial tiles and X(l) were
 // published by other workgroups of the same launch. No barrier at the end.
-template <int L, int T, int DT, bool COHERENT>
+template <int L, int T, int DT, bool COHERENT, bool ACC = false>
 __device__ __forceinline__ void channel_spectrum(const DevPlan& P, const float2* __restrict__ ypart,
                                                  const typename Store<DT>::T* __restrict__ bank,
                                                  const typename Store<DT>::T* __restrict__ fdl,
@@ -375,7 +375,8 @@ __device__ __forceinline__ void channel_spectrum(const DevPlan& P, const float2*
       s0 = cadd(s0, a0); s1 = cadd(s1, a1); s2 = cadd(s2, a2); s3 = cadd(s3, a3);
     }
     for (; j < nch; ++j) s0 = cadd(s0, load_maybe<COHERENT>(src + (int64_t)j * TW));
-    Y[k] = cadd(cadd(s0, s1), cadd(s2, s3));
+    const float2 v = cadd(cadd(s0, s1), cadd(s2, s3));
+    Y[k] = ACC ? cadd(Y[k], v) : v;   // ACC: add to the bus sum (each thread owns its k)
   }
 }
 
@@ -966,10 +967,288 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
   }
 }
 
+// Matrix-core form of the time-blocked MAC (eq. 8) for f32 spectra. For one
+// bin, a time group of 16 blocks of one parity class and the (up to) two
+// channels of one input, the products form outer products of delay-line and
+// partition spectra. One 4x4x1 MFMA with 16 blocks takes 16 bins: in each
+// block, rows are (Re, Im) of X for two blocks t and t + 8 and columns (Re,
+// Im) of H for the two channels; its 4x4 accumulator collects the four real
+// products Re X Re H, Im X Re H, Re X Im H, Im X Im H of every (block,
+// channel), combined into Re Y and Im Y once after the last partition. Pair q
+// (blocks q and q + 8) at partition m + 1 needs the delay-line values that
+// pair q - 1 used at m, so each lane keeps a circular window of 8 values per
+// bin that moves down one pair per partition; only pair 0 is loaded afresh.
+// Even and odd pairs may take different slots (a stream that switches every
+// block alternates two slots in a parity class); other slot patterns run
+// passes in which the blocks of other slots are masked out of the A operand.
+// A wave covers 16 U bins (U sub-tiles of 16); PD partitions are loaded ahead.
+template <int L, int U, int PD, int DT>
+__global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
+  static_assert(DT == 0, "matrix-core MAC: f32 spectra");
+  static_assert(U == 1 || U == 2 || U == 4, "sub-tiles per wave");
+  static_assert(PD == 2 || PD == 4 || PD == 8, "prefetch depth divides the window");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int TB = 16;
+  constexpr int N = 2 * L;
+  constexpr int RS = 2 * N;                 // floats per delay-line / partition row
+  const int TW = B.tile_width;              // 16 U bins per wave
+  const DevPlan& P = B.P;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int b16 = lane >> 2;                // bin of the lane's MFMA block
+  const int hh = (lane >> 1) & 1;           // A: block half (t = q + 8 hh); B and C: channel
+  const int comp = lane & 1;                // Re (0) or Im (1)
+  const uint64_t cnt0 = *B.counter;
+  const int n = B.n_blocks;
+  const int groups = ((n + 1) / 2 + TB - 1) / TB;
+  // same XCD-aware index space as k_tmac
+  const int pairs = 2 * B.n_mac;
+  const int lanes8 = (pairs + 7) / 8;
+  const int total = 8 * lanes8 * groups;
+  const float* bank = static_cast<const float*>(B.bank);
+  const float* fdl = static_cast<const float*>(B.fdl);
+  for (int idx = blockIdx.x; idx < total; idx += gridDim.x) {
+    const int x = idx & 7, y = idx >> 3;
+    const int gi = y % groups;
+    const int pr = x + 8 * (y / groups);
+    if (pr >= pairs) continue;
+    const int cls = pr & 1;
+    const WorkItem it = B.items[pr >> 1];
+    const int j0 = cls + 2 * TB * gi;
+    if (j0 >= n) continue;
+    const int nb = min(TB, (n - j0 + 1) / 2);
+    const int i = uniform(it.input);
+    const int n_ch = uniform(it.n_ch);
+    const int m0 = uniform(it.m0), m1 = uniform(it.m1);
+    const int Mi = uniform(P.in_M[i]);
+    const uint64_t c0 = cnt0 + (uint64_t)j0;
+    const int p = (int)(c0 & 1u);
+    const int qh = hh ? ring_slot(c0 + 16u, Mi) : ring_slot(c0, Mi);   // ring slot of block 8 hh
+    const uint32_t f0 = 2u * (uint32_t)(it.tile * TW + w * 16 * U + b16) + (uint32_t)comp;   // float in a row
+    const float* xb = fdl + 2 * (P.in_fdl_off[i] + (int64_t)p * Mi * N);
+    int ch[2], McL[2], Mc[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      ch[g] = uniform(g < n_ch ? it.ch[g] : it.ch[0]);
+      McL[g] = uniform(P.ch_M[ch[g]]);
+      Mc[g] = g < n_ch ? McL[g] : 0;
+    }
+    int slot[2][TB];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) slot[g][b] = B.sel[(int64_t)(j0 + 2 * min(b, nb - 1)) * B.sel_stride + ch[g]];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int sv = uniform(slot[g][b]);
+        slot[g][b] = sv < 0 ? 0 : (sv >= P.K ? P.K - 1 : sv);
+      }
+    // the lane's channel (B operand) and its partition range
+    const int Mcl = hh ? Mc[1] : Mc[0];
+    const int mlast = min(m1, hh ? McL[1] : McL[0]) - 1;
+    const float* hch = bank + 2 * (hh ? P.ch_bank_off[ch[1]] : P.ch_bank_off[ch[0]]);
+    const int64_t slot_stride = (int64_t)(hh ? McL[1] : McL[0]) * RS;
+
+    f4 acc[8][U];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[q][u] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // One pass over the partitions [m0, m1). Even pairs take the spectra at
+    // he, odd pairs those at ho; rows of blocks outside `act` are masked out
+    // of the A operand. (A single code path: variants of it would each hold
+    // their own copy of the accumulators.)
+    auto run = [&](const float* he, const float* ho, uint32_t act) {
+      constexpr int ND = 2;
+      // Delay-line values by d = q - s (pair q at step s = mm - m0), in a
+      // circular buffer of R = 8 + PD registers per bin: d = 7 - s .. -s are
+      // in use at step s, d = -s - 1 .. -s - PD are in flight, and the load
+      // for d = -s - 1 - PD reuses the register of d = 7 - s after step s.
+      constexpr int R = 8 + PD;
+      float W[R][U];
+      auto load_x = [&](float (&o)[U], int d) {   // X of block 8 hh + d at partition m0
+        int r = (qh + d - m0) % Mi;
+        r = r < 0 ? r + Mi : r;
+        const float* src = xb + (uint32_t)r * RS + f0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) o[u] = src[32 * u];
+      };
+      auto load_xs = [&](float (&o)[U], int s) {  // d = -s (pair 0 at step s), s >= 1
+        int r = qh - min(m0 + s, m1 - 1);
+        r = r < 0 ? r + Mi : r;
+        const float* src = xb + (uint32_t)r * RS + f0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) o[u] = src[32 * u];
+      };
+      float Hq[PD][ND][U];
+      auto load_h = [&](float (&o)[ND][U], int mm) {
+        const uint32_t off = (uint32_t)min(mm, mlast) * RS + f0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          const float* src = (d == 0 ? he : ho) + off;
+#pragma unroll
+          for (int u = 0; u < U; ++u) o[d][u] = src[32 * u];
+        }
+      };
+#pragma unroll
+      for (int q = 0; q < 8; ++q) load_x(W[q], q);
+#pragma unroll
+      for (int k = 0; k < PD; ++k) {
+        load_h(Hq[k], m0 + k);
+        load_xs(W[R - 1 - k], k + 1);   // d = -(k + 1)
+      }
+      // step s (S = s mod R, s = mm - m0)
+      auto advance = [&](int mm, auto sc) {
+        constexpr int S = decltype(sc)::value;
+        const bool on = mm < Mcl;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          float bq[ND];
+#pragma unroll
+          for (int d = 0; d < ND; ++d) bq[d] = on ? Hq[S % PD][d][u] : 0.f;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            float a = W[(((q - S) % R) + R) % R][u];
+            a = ((act >> (q + 8 * hh)) & 1u) ? a : 0.f;
+            acc[q][u] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, bq[q & 1], acc[q][u], 0, 0, 0);
+          }
+        }
+        load_h(Hq[S % PD], mm + PD);
+        load_xs(W[(((7 - S) % R) + R) % R], mm - m0 + 1 + PD);
+      };
+      int mb = m0;
+      for (; mb + R <= m1; mb += R) static_for<R>([&](auto sc) { advance(mb + decltype(sc)::value, sc); });
+      static_for<R>([&](auto sc) {
+        if (mb + decltype(sc)::value < m1) advance(mb + decltype(sc)::value, sc);
+      });
+    };
+
+    // passes: the even pairs take the slots of the first even block not yet
+    // done, the odd pairs those of the first odd one; blocks with other slots
+    // wait for a later pass
+    const uint32_t all = (1u << nb) - 1u;
+    uint32_t todo = all;
+    while (todo != 0u) {
+      int te = -1, to = -1;
+#pragma unroll
+      for (int b = TB - 1; b >= 0; --b)
+        if ((todo >> b) & 1u) {
+          if (b & 1) to = b;
+          else te = b;
+        }
+      if (te < 0) te = to;
+      if (to < 0) to = te;
+      int se[2] = {0, 0}, so[2] = {0, 0};
+#pragma unroll
+      for (int b = 0; b < TB; ++b)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          if (b == te) se[g] = slot[g][b];
+          if (b == to) so[g] = slot[g][b];
+        }
+      uint32_t act = 0u;
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const bool ev = (b & 1) == 0;
+        if (((todo >> b) & 1u) && slot[0][b] == (ev ? se[0] : so[0]) && slot[1][b] == (ev ? se[1] : so[1]))
+          act |= 1u << b;
+      }
+      todo &= ~act;
+      run(hch + (hh ? se[1] : se[0]) * slot_stride, hch + (hh ? so[1] : so[0]) * slot_stride,
+          act | ~all);
+    }
+
+    // Re Y = ReX ReH - ImX ImH (Re lane), Im Y = ReX ImH + ImX ReH (Im lane);
+    // the packed DC / Nyquist bin takes ReX ReH and ImX ImH
+    const bool dcl = it.tile == 0 && w == 0 && b16 == 0;
+    const int rowl = hh ? it.row[1] : it.row[0];
+    const bool wr = hh < n_ch;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const f4 c = acc[q][u];
+        const float p1 = __shfl_xor(c[1], 1);
+        const float p3 = __shfl_xor(c[3], 1);
+#pragma unroll
+        for (int h2 = 0; h2 < 2; ++h2) {
+          const int t = q + 8 * h2;
+          const float cr = h2 ? c[2] : c[0];
+          const float ci = h2 ? c[3] : c[1];
+          const float pi = h2 ? p3 : p1;
+          float v = comp ? cr + pi : cr - pi;
+          if (dcl && u == 0) v = comp ? ci : cr;
+          if (t < nb && wr) {
+            float* dst = reinterpret_cast<float*>(B.ypart + ((int64_t)(j0 + 2 * t) * B.n_rows + rowl) * TW) +
+                         2 * (w * 16 * U + 16 * u) + (f0 & 31u);
+            *dst = v;
+          }
+        }
+      }
+  }
+}
+
+// Mixdown of a batch: for block j, bus e and 64 bins, the sum over the bus's
+// channels and their partition chunks of the partial rows (the channels'
+// spectra Y, eq. 8, are added before one inverse transform per bus), written
+// over the first channel's chunk-0 row, which k_batch_inv then reads alone.
+// Four slices of the channel list are summed apart (four channels' loads in
+// flight per thread) and added in a fixed order.
+template <int L>
+__global__ __launch_bounds__(256) void k_bus_sum(BatchArgs B) {
+  const DevPlan& P = B.P;
+  const int tid = threadIdx.x, kx = tid & 63, sl = tid >> 6;
+  const int k = blockIdx.x * 64 + kx;
+  const int e = blockIdx.y, j = blockIdx.z;
+  const int TW = B.tile_width;
+  const int t = k / TW, kk = k - t * TW;
+  const int c0 = P.out_ptr[e], c1 = P.out_ptr[e + 1];
+  float2* yp = B.ypart + (int64_t)j * B.n_rows * TW;
+  float2 a[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) a[r] = make_float2(0.f, 0.f);
+  // this slice's channels c0 + sl + 4 i, four at a time
+  for (int q = c0 + sl; q < c1; q += 16) {
+    const float2* src[4];
+    int nch[4];
+    int mx = 0;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int qq = q + 4 * x;
+      nch[x] = 0;
+      src[x] = yp;
+      if (qq < c1) {
+        const int c = P.out_ch[qq];
+        nch[x] = B.nchunks[c];
+        src[x] = yp + ((int64_t)B.row_base[c] + (int64_t)t * nch[x]) * TW + kk;
+      }
+      mx = max(mx, nch[x]);
+    }
+    for (int r = 0; r < mx; ++r) {
+      float2 v[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) v[x] = (r < nch[x]) ? src[x][(int64_t)r * TW] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) a[x] = cadd(a[x], v[x]);
+    }
+  }
+  __shared__ float2 red[4][64];
+  red[sl][kx] = cadd(cadd(a[0], a[1]), cadd(a[2], a[3]));
+  __syncthreads();
+  if (sl == 0) {
+    const float2 v = cadd(cadd(red[0][kx], red[1][kx]), cadd(red[2][kx], red[3][kx]));
+    const int cf = P.out_ch[c0];
+    yp[((int64_t)B.row_base[cf] + (int64_t)t * B.nchunks[cf]) * TW + kk] = v;
+  }
+}
+
 // Block j, channel c of a batch: the sum of the channel's partial rows (all
 // partitions, eq. 8) and the inverse transform (eq. 9) into the block buffer.
 template <int L>
-__global__ __launch_bounds__(256) void k_batch_inv(BatchArgs B) {
+__global__ __launch_bounds__(256) void k_batch_inv(BatchArgs B, int bpw) {
   constexpr int N = 2 * L;
   constexpr int T = 256;
   __shared__ float2 twl[2 * N];
@@ -978,32 +1257,40 @@ __global__ __launch_bounds__(256) void k_batch_inv(BatchArgs B) {
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
   const DevPlan& P = B.P;
-  const int c = blockIdx.x, tid = threadIdx.x;
+  const int e = blockIdx.x, tid = threadIdx.x;    // output bus
   load_tables<L, T>(P, twl, winl, tid);
   const int TW = B.tile_width;
-  const int base = B.row_base[c];
-  const int nch = B.nchunks[c];
-  // kBatchBlocksPerWg consecutive blocks per workgroup (tables loaded once)
-  for (int u = 0; u < kBatchBlocksPerWg; ++u) {
-    const int j = blockIdx.y * kBatchBlocksPerWg + u;
+  const int c0 = P.out_ptr[e];
+  // with bus sums in place (B.bus_rows), the first channel's chunk-0 rows hold the bus
+  const int c1 = B.bus_rows ? c0 + 1 : P.out_ptr[e + 1];
+  // bpw consecutive blocks per workgroup (tables loaded once)
+  for (int u = 0; u < bpw; ++u) {
+    const int j = blockIdx.y * bpw + u;
     if (j >= B.n_blocks) break;
     const float2* yp = B.ypart + (int64_t)j * B.n_rows * TW;
     for (int k = tid; k < N; k += T) {
       const int t = k / TW;
       const int kk = k - t * TW;
-      const float2* src = yp + ((int64_t)base + (int64_t)t * nch) * TW + kk;
-      float2 s0 = src[0];
-      float2 s1 = make_float2(0.f, 0.f);
-      int q = 1;
-      for (; q + 1 < nch; q += 2) {
-        s0 = cadd(s0, src[(int64_t)q * TW]);
-        s1 = cadd(s1, src[(int64_t)(q + 1) * TW]);
+      float2 acc = make_float2(0.f, 0.f);
+      for (int qc = c0; qc < c1; ++qc) {
+        const int c = P.out_ch[qc];
+        const int nrow = B.nchunks[c];
+        const int nch = B.bus_rows ? 1 : nrow;
+        const float2* src = yp + ((int64_t)B.row_base[c] + (int64_t)t * nrow) * TW + kk;
+        float2 s0 = src[0];
+        float2 s1 = make_float2(0.f, 0.f);
+        int q = 1;
+        for (; q + 1 < nch; q += 2) {
+          s0 = cadd(s0, src[(int64_t)q * TW]);
+          s1 = cadd(s1, src[(int64_t)(q + 1) * TW]);
+        }
+        if (q < nch) s0 = cadd(s0, src[(int64_t)q * TW]);
+        acc = (qc == c0) ? cadd(s0, s1) : cadd(acc, cadd(s0, s1));
       }
-      if (q < nch) s0 = cadd(s0, src[(int64_t)q * TW]);
-      Y[k] = cadd(s0, s1);
+      Y[k] = acc;
     }
     __syncthreads();
-    inverse_store<L, T>(Y, bufA, bufB, twl, B.yblk + ((int64_t)j * P.C + c) * 4 * L, tid);
+    inverse_store<L, T>(Y, bufA, bufB, twl, B.yblk + ((int64_t)j * P.n_out + e) * 4 * L, tid);
     __syncthreads();
   }
 }
@@ -1032,10 +1319,10 @@ __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __r
   // the history parity); they alone count towards advancing it
   const uint64_t cnt0 = (sw == 0) ? *B.counter : 0;
   __shared__ int last;
-  if (c < P.C) {
+  if (c < P.n_out) {                       // output bus c
     float* st = ola + (int64_t)c * 3 * L;
-    const float* yc = B.yblk + (int64_t)c * 4 * L;     // block j at yc + j * C * 4L
-    const int64_t ystride = (int64_t)P.C * 4 * L;
+    const float* yc = B.yblk + (int64_t)c * 4 * L;     // block j at yc + j * n_out * 4L
+    const int64_t ystride = (int64_t)P.n_out * 4 * L;
     float* oc = out + (int64_t)c * out_stride;
     const int t0 = sw * SPW;
     float v[R];
@@ -1089,7 +1376,9 @@ __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __r
       }
       if (tid == 0) {
         B.arrive[c] = 0;
-        if (B.copy_sel) B.sel_store[c] = B.sel[(int64_t)(n - 1) * B.sel_stride + c];
+        if (B.copy_sel)
+          for (int q = P.out_ptr[c]; q < P.out_ptr[c + 1]; ++q)
+            B.sel_store[P.out_ch[q]] = B.sel[(int64_t)(n - 1) * B.sel_stride + P.out_ch[q]];
       }
     }
   }
@@ -1144,8 +1433,9 @@ __global__ __launch_bounds__(64 * NW) void k_mac(DevPlan P, const WorkItem* __re
   write_partials<V, G, NW, false>(it, acc, red, ypart, tid & 63, tid >> 6, tid);
 }
 
-// One workgroup per channel: complete the channel; the last workgroup to
-// finish advances the call count.
+// One workgroup per output bus: the sum of its channels' spectra, the inverse
+// transform and the overlap-add; the last workgroup to finish advances the
+// call count.
 template <int L, int DT>
 __global__ __launch_bounds__(64) void k_inv(DevPlan P, const float2* __restrict__ ypart,
                                             const typename Store<DT>::T* __restrict__ bank,
@@ -1160,14 +1450,23 @@ __global__ __launch_bounds__(64) void k_inv(DevPlan P, const float2* __restrict_
   __shared__ float2 Y[N];
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
-  const int c = blockIdx.x;
+  const int e = blockIdx.x;
   const int tid = threadIdx.x;
   const uint64_t cnt = *counter;
+  const int p = (int)(cnt & 1u);
   load_tables<L, 64>(P, twl, winl, tid);
-  channel_final<L, 64, DT, false>(P, ypart, bank, fdl, sel, c, (int)(cnt & 1u), cnt, Y, bufA, bufB, twl, ola, out,
-                                  out_stride, tid);
+  float* st = ola + (int64_t)e * 3 * L;
+  float old[(4 * L + 63) / 64];
+  ola_prefetch<L, 64>(st, old, tid);
+  const int c0 = P.out_ptr[e], c1 = P.out_ptr[e + 1];
+  channel_spectrum<L, 64, DT, false>(P, ypart, bank, fdl, sel, P.out_ch[c0], p, cnt, Y, tid);
+  for (int q = c0 + 1; q < c1; ++q)
+    channel_spectrum<L, 64, DT, false, true>(P, ypart, bank, fdl, sel, P.out_ch[q], p, cnt, Y, tid);
+  __syncthreads();
+  inverse_ola<L, 64>(Y, bufA, bufB, twl, old, st, out + (int64_t)e * out_stride, tid);
   if (tid == 0) {
-    if (copy_sel) sel_store[c] = sel[c];
+    if (copy_sel)
+      for (int q = c0; q < c1; ++q) sel_store[P.out_ch[q]] = sel[P.out_ch[q]];
     if (atomicAdd(done, 1) == (int)gridDim.x - 1) {
       *done = 0;
       *counter = cnt + 1u;
@@ -1330,7 +1629,7 @@ hipError_t hop_inv(const DevPlan& P, int dtype, const float2* ypart, const void*
   return by_dtype(dtype, [&](auto Dc) {
     constexpr int DT = decltype(Dc)::value;
     using ST = typename Store<DT>::T;
-    hipLaunchKernelGGL((k_inv<L, DT>), dim3(P.C), dim3(64), 0, s, P, ypart, static_cast<const ST*>(bank),
+    hipLaunchKernelGGL((k_inv<L, DT>), dim3(P.n_out), dim3(64), 0, s, P, ypart, static_cast<const ST*>(bank),
                        static_cast<const ST*>(fdl), sel, ola, out, out_stride, copy_sel, sel_store, done, counter);
     return hipGetLastError();
   });
@@ -1370,6 +1669,18 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if (B.n_mac > 0) {
+      if (shape.E == 1) {
+        // matrix-core MAC: f32 spectra, up to two channels per item, time groups of 16
+        if constexpr (DT == 0) {
+          if (shape.G > 2 || B.time_block != 16 || shape.V != 1) return hipErrorInvalidValue;
+          if (shape.NW != 1 && shape.NW != 2 && shape.NW != 4) return hipErrorInvalidValue;
+          if (16 * shape.NW != B.tile_width || B.tile_width > 2 * L) return hipErrorInvalidValue;
+          hipLaunchKernelGGL((k_tmfma<L, 1, 4, DT>), dim3(grid), dim3(64 * shape.NW), 0, s, B);
+          e = hipGetLastError();
+        } else {
+          return hipErrorInvalidValue;
+        }
+      } else {
       e = by_bshape(shape, [&](auto Vc, auto Gc) {
         constexpr int V = decltype(Vc)::value, G = decltype(Gc)::value;
         if (shape.NW != 1 && shape.NW != 2 && shape.NW != 4) return hipErrorInvalidValue;
@@ -1384,13 +1695,21 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
         }
         return hipGetLastError();
       });
+      }
       if (e != hipSuccess) return e;
     }
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_batch_inv<L>), dim3(B.P.C, bgroups), dim3(256), 0, s, B);
+    if (B.bus_rows) {
+      hipLaunchKernelGGL((k_bus_sum<L>), dim3(2 * L / 64, B.P.n_out, B.n_blocks), dim3(256), 0, s, B);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    // few outputs: one block per workgroup, for more workgroups
+    const int bpw = (B.P.n_out * bgroups < 256) ? 1 : kBatchBlocksPerWg;
+    hipLaunchKernelGGL((k_batch_inv<L>), dim3(B.P.n_out, (B.n_blocks + bpw - 1) / bpw), dim3(256), 0, s, B, bpw);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int wgs = B.P.C > B.P.I ? B.P.C : B.P.I;
+    const int wgs = B.P.n_out > B.P.I ? B.P.n_out : B.P.I;
     const int spw = (B.n_blocks * L + 4 * 256 - 1) / (4 * 256);   // 4 samples per thread, 256 threads
     hipLaunchKernelGGL((k_batch_ola<L>), dim3(wgs, spw), dim3(256), 0, s, B, in, in_stride, hist, B.ola_state, out,
                        out_stride);

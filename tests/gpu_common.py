@@ -40,6 +40,17 @@ def oracle_streams(wl, channels=None, dtype: str = "f32") -> np.ndarray:
     return out
 
 
+def oracle_bus_streams(wl, buses, dtype: str = "f32") -> np.ndarray:
+    """FP64 oracle of a mixdown: bus e is the sum of the oracle streams of the
+    channels c with buses[c] == e. Returns [n_buses][n_calls*L]."""
+    buses = np.asarray(buses)
+    per = oracle_streams(wl, None, dtype)
+    out = np.zeros((int(buses.max()) + 1, per.shape[1]))
+    for c in range(wl.n_channels):
+        out[int(buses[c])] += per[c]
+    return out
+
+
 MODES = {
     "fused": dict(fused=1),
     "plain": dict(fused=0),
@@ -51,13 +62,15 @@ MODES = {
 }
 
 
-def make_convolver(wl, dtype: str = "f32", stream=None, mode: str = "fused", max_batch: int = 16):
+def make_convolver(wl, dtype: str = "f32", stream=None, mode: str = "fused", max_batch: int = 16, buses=None):
+    """buses: None (one output per channel) or [C] bus of each channel (mixdown)."""
     from paper_2310_00319_amd import Convolver
 
+    mix = {} if buses is None else dict(n_outputs=int(np.max(buses)) + 1, output_of_channel=buses)
     conv = Convolver(hop=wl.hop, n_channels=wl.n_channels, max_taps=wl.max_taps(),
                      n_inputs=wl.n_inputs, input_of_channel=wl.input_of_channel,
                      taps_of_channel=wl.taps_of_channel, n_slots=wl.n_slots, dtype=dtype, stream=stream,
-                     max_batch=max_batch)
+                     max_batch=max_batch, **mix)
     if mode != "fused":
         conv.configure(**MODES[mode])
     for c in range(wl.n_channels):
@@ -66,14 +79,14 @@ def make_convolver(wl, dtype: str = "f32", stream=None, mode: str = "fused", max
     return conv
 
 
-def gpu_streams(wl, dtype: str = "f32", conv=None, mode: str = "fused", batch: int = 1):
+def gpu_streams(wl, dtype: str = "f32", conv=None, mode: str = "fused", batch: int = 1, buses=None):
     """Whole workload through the library with a device-resident schedule.
-    Returns the [C][n_calls*L] output as float64 numpy."""
+    Returns the [C][n_calls*L] output (one row per bus with `buses`) as float64 numpy."""
     import torch
 
     own = conv is None
     if own:
-        conv = make_convolver(wl, dtype, mode=mode)
+        conv = make_convolver(wl, dtype, mode=mode, buses=buses)
     x = torch.from_numpy(wl.padded_input()).cuda()
     sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
     out = conv.process(x, sched, batch=batch)
@@ -84,20 +97,25 @@ def gpu_streams(wl, dtype: str = "f32", conv=None, mode: str = "fused", batch: i
     return res
 
 
-def gpu_streams_graph(wl, dtype: str = "f32", batch: int = 64, channels=None, tune: bool = True):
+def gpu_streams_graph(wl, dtype: str = "f32", batch: int = 64, channels=None, tune: bool = True, buses=None,
+                      schedule: dict | None = None):
     """The benchmark's launch configuration: calls of `batch` blocks (max_batch
     = batch, batched schedule autotuned), captured once as a HIP graph on a
-    side stream and replayed. Returns [len(channels)][n_calls*L] float64."""
+    side stream and replayed. Returns [len(channels)][n_calls*L] float64
+    (`channels` index the buses with a mixdown). `schedule`: configure_batch
+    arguments instead of the autotuner."""
     import torch
 
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        conv = make_convolver(wl, dtype, stream=stream, max_batch=batch)
-        if tune:
+        conv = make_convolver(wl, dtype, stream=stream, max_batch=batch, buses=buses)
+        if schedule is not None:
+            conv.configure_batch(**schedule)
+        elif tune:
             conv.autotune_batch(iters=2)
         x = torch.from_numpy(wl.padded_input()).cuda()
         sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
-        out = torch.zeros((wl.n_channels, wl.n_calls * wl.hop), device="cuda")
+        out = torch.zeros((conv.n_outputs, wl.n_calls * wl.hop), device="cuda")
         stream.synchronize()
         conv.capture_begin()
         conv.process(x, sched, out, batch=batch)
@@ -105,7 +123,7 @@ def gpu_streams_graph(wl, dtype: str = "f32", batch: int = 64, channels=None, tu
         conv.reset()
         conv.graph_launch()
         stream.synchronize()
-        chans = list(range(wl.n_channels)) if channels is None else list(channels)
+        chans = list(range(conv.n_outputs)) if channels is None else list(channels)
         res = out[chans].cpu().numpy().astype(np.float64)
         conv.close()
     return res

@@ -81,6 +81,24 @@ def test_create_rejects_bad_maps(lib):
     assert "taps_of_channel" in lib.tvolap_last_error(None).decode()
 
 
+@pytest.mark.parametrize("n_out,bus,msg", [
+    (3, None, "n_outputs must be in"),
+    (-1, None, "n_outputs must be in"),
+    (1, None, "output_of_channel is NULL"),
+    (2, (0, 2), "output_of_channel value out of range"),
+    (2, (1, 1), "every output needs at least one channel"),
+])
+def test_create_rejects_bad_mixdown(lib, n_out, bus, msg):
+    h = ctypes.c_void_p()
+    cfg = _cfg(n_outputs=n_out)
+    if bus is not None:
+        arr = (ctypes.c_int32 * 2)(*bus)
+        cfg.output_of_channel = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+    assert lib.tvolap_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert h.value is None
+    assert msg in lib.tvolap_last_error(None).decode()
+
+
 def test_null_arguments(lib):
     h = ctypes.c_void_p()
     assert lib.tvolap_create(None, ctypes.byref(h)) == -1
@@ -88,7 +106,7 @@ def test_null_arguments(lib):
     assert lib.tvolap_destroy(None) == 0
     assert lib.tvolap_process_block(None, None, 0, None, 0, None) == -1
     assert lib.tvolap_set_irs(None, 0, None, 1) == -1
-    assert lib.tvolap_configure_batch(None, 0, 0, 0, 0, 0) == -1
+    assert lib.tvolap_configure_batch(None, 0, 0, 0, 0, 0, 0) == -1
     assert lib.tvolap_version().decode().startswith("tvolap")
 
 

@@ -446,3 +446,88 @@ def test_batched_mixed_with_single_calls_and_host_selection():
     conv.close()
     assert rel_rms_per_channel(got, ref).max() <= 1e-6
     assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
+
+
+# ------------------------------------------------------------------ matrix-core engine
+
+@pytest.mark.parametrize("case", SMALL_CASES, ids=[f"s{c[0]}_L{c[1]}" for c in SMALL_CASES])
+@pytest.mark.parametrize("batch", [2, 5, 16])
+def test_matrix_core_engine_matches_single_blocks_and_oracle(case, batch):
+    """The batched MAC on matrix cores (4x4 outer products per bin, one MFMA
+    per 16 bins) agrees with single-block calls to FP32 rounding and with the
+    oracle; the cases switch slots irregularly (masked passes), have ragged
+    partition counts within an input and partial time groups."""
+    seed, L, C, I, N, tr, K, p = case
+    log(f"matrix-core engine case {case} batch {batch}")
+    wl = synth.random_small(seed=seed, hop=L, n_channels=C, n_inputs=I, n_samples=N,
+                            taps_range=tr, n_slots=K, p_switch=p)
+    single = gpu_streams(wl)
+    conv = make_convolver(wl)
+    conv.configure_batch(engine=2)
+    info = conv.info()
+    assert info["batch_engine"] == 2 and info["batch_time_block"] == 16
+    got = gpu_streams(wl, conv=conv, batch=batch)
+    conv.close()
+    assert rel_rms_per_channel(got, single).max() <= 1e-6
+    assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
+
+
+# (chunk, waves, group) of the matrix-core engine
+MFMA_SCHEDULES = [(0, 0, 0), (2, 1, 1), (3, 2, 2), (1, 4, 1), (200, 1, 2), (5, 2, 1)]
+
+
+@pytest.mark.parametrize("sched", MFMA_SCHEDULES, ids=[f"c{s[0]}w{s[1]}g{s[2]}" for s in MFMA_SCHEDULES])
+@pytest.mark.parametrize("case", [SMALL_CASES[1], SMALL_CASES[4], SMALL_CASES[3]], ids=["s2_L128", "s5_L64", "s4_L512"])
+def test_matrix_core_engine_schedules(case, sched):
+    seed, L, C, I, N, tr, K, p = case
+    chunk, waves, group = sched
+    log(f"matrix-core schedule {sched} case {case}")
+    wl = synth.random_small(seed=seed + 100, hop=L, n_channels=C, n_inputs=I, n_samples=N,
+                            taps_range=tr, n_slots=K, p_switch=p)
+    conv = make_convolver(wl, max_batch=32)
+    conv.configure_batch(chunk=chunk, waves=waves, group=group, engine=2)
+    got = gpu_streams(wl, conv=conv, batch=11)
+    conv.close()
+    assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
+
+
+@pytest.mark.parametrize("batch", [64, 37, 23])
+def test_matrix_core_engine_large_batches(batch):
+    log(f"matrix-core large batch {batch}")
+    wl = synth.random_small(seed=78, hop=128, n_channels=8, n_inputs=4, n_samples=128 * 150 + 9,
+                            taps_range=(300, 9000), n_slots=3, p_switch=0.3)
+    conv = make_convolver(wl, max_batch=64)
+    conv.configure_batch(engine=2)
+    got = gpu_streams(wl, conv=conv, batch=batch)
+    conv.close()
+    assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
+
+
+def test_matrix_core_engine_rejected_for_16_bit_spectra():
+    wl = synth.random_small(seed=79, hop=64, n_channels=2, n_inputs=1, n_samples=64 * 10,
+                            taps_range=(10, 300), n_slots=1, p_switch=0.0)
+    conv = make_convolver(wl, "bf16")
+    with pytest.raises(Exception, match="matrix-core"):
+        conv.configure_batch(engine=2)
+    conv.close()
+
+
+def test_full_binaural_bench_configuration_matrix_cores():
+    log("full binaural, 64-block calls from a graph, matrix-core engine")
+    wl = synth.binaural()
+    chans = [0, 1, 62, 63, 126, 127]
+    got = gpu_streams_graph(wl, batch=64, channels=chans, schedule=dict(engine=2))
+    err = rel_rms_per_channel(got, oracle_streams(wl, chans))
+    log(f"binaural bench configuration (matrix cores): max rel-RMS {err.max():.3e}")
+    assert err.max() <= TOL_F32
+
+
+def test_full_uneven_bench_configuration_matrix_cores():
+    log("full uneven, 64-block calls from a graph, matrix-core engine")
+    wl = synth.uneven()
+    lens = wl.taps_of_channel
+    chans = sorted({int(np.argmax(lens)), int(np.argmin(lens)), 0, 255, 511})
+    got = gpu_streams_graph(wl, batch=64, channels=chans, schedule=dict(engine=2))
+    err = rel_rms_per_channel(got, oracle_streams(wl, chans))
+    log(f"uneven bench configuration (matrix cores): max rel-RMS {err.max():.3e}")
+    assert err.max() <= TOL_F32
