@@ -234,8 +234,8 @@ int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us);
  * feeds several channels); engine: 1 = vector ALU (multiply-adds or packed
  * dot products per complex product), 2 = matrix cores (f32 spectra only: per
  * bin, the products of a time group of 16 blocks and the two channels of an
- * input are 4x4 outer products, one 16-bin MFMA each; needs time groups of 16
- * and vec 1, which it implies), 0 = 1. Waits for the stream; rebuilds the
+ * input are 4x4 outer products, one 16-bin MFMA each; implies time groups of
+ * 16 and 16 bins per wave, so vec must be 0 or 1), 0 = 1. Waits for the stream; rebuilds the
  * batched work list. Errors: EINVAL (also engine 2 with 16-bit spectra),
  * ESTATE during capture, ENOMEM/EDEVICE. */
 int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block,

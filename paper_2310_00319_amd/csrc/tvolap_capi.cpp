@@ -71,6 +71,8 @@ struct tvolap {
   int32_t max_batch = 16, ring_extra = 7;
   std::vector<int64_t> ch_bank_off, in_fdl_off;
   int64_t bank_elems = 0, fdl_elems = 0;
+  int32_t bank_pad_rows = 0;    // zero partition rows allocated after the bank
+  size_t bank_alloc_bytes = 0;  // bank and padding; the delay line follows in the same allocation
   size_t store_bytes = 8;  // bytes per stored complex value
 
   // device buffers
@@ -224,7 +226,7 @@ void free_all(tvolap_t* h) {
   h->graph = nullptr;
   free_work(h);
   free_batch_work(h);
-  dfree(h->d_bank); dfree(h->d_fdl); dfree(h->d_hist); dfree(h->d_ola); dfree(h->d_sel);
+  dfree(h->d_bank); h->d_fdl = nullptr; dfree(h->d_hist); dfree(h->d_ola); dfree(h->d_sel);
   dfree(h->d_out_ptr); dfree(h->d_out_ch);
   dfree(h->d_counter); dfree(h->d_tw); dfree(h->d_win); dfree(h->d_ch_input); dfree(h->d_ch_M);
   dfree(h->d_ch_bank_off); dfree(h->d_in_M); dfree(h->d_in_fdl_off); dfree(h->d_taps);
@@ -348,24 +350,47 @@ void build_work(tvolap_t* h, int S_req, int waves, int vec) {
 // group's partitions [0, M) cut into chunks of S. The partial rows of a
 // channel are contiguous in (tile, chunk) order. Each item runs once per
 // time group (a parity class of up to b_tb (8 or 16) blocks of the call).
+// The matrix-core MAC addresses the partition spectra of an item's channels
+// and the delay line of its input with 32-bit byte offsets from one base.
+bool mfma_offsets_fit(const tvolap_t* h) {
+  const int64_t N = 2 * h->L, lim = (int64_t)1 << 32;
+  for (int c = 0; c < h->C; ++c) {
+    // channel c and every later channel of the same input (pairs are formed in increasing order)
+    for (int c2 = c; c2 < h->C; ++c2) {
+      if (h->ch_input[c2] != h->ch_input[c]) continue;
+      const int64_t span = h->ch_bank_off[c2] - h->ch_bank_off[c] + (int64_t)h->K * h->ch_M[c2] * N +
+                           (int64_t)h->bank_pad_rows * N;
+      if (span * 8 >= lim) return false;
+    }
+  }
+  if ((int64_t)h->bank_alloc_bytes + h->fdl_elems * 8 >= lim) return false;   // delay line from the bank base
+  return true;
+}
+
 void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   const int N = 2 * h->L;
   // time groups of 16 blocks (one bin per lane) when calls can hold 32 blocks
   int V = (bc.vec == 1) ? 1 : 2;
   int TB = bc.time_block == 16 ? 16 : (bc.time_block == 8 ? 8 : (h->max_batch >= 32 ? 16 : 8));
   const int engine = (bc.engine == 2 && h->dtype == 0) ? 2 : 1;
-  if (engine == 2) { TB = 16; V = 1; }   // matrix cores: time groups of 16, 64 bins per wave
-  h->bshape.E = engine == 2 ? 1 : 0;
-  if (TB == 16 && bc.vec == 0) V = 1;
-  if (TB == 16 && V != 1) TB = 8;
+  h->bshape.E = (engine == 2 && mfma_offsets_fit(h)) ? 1 : 0;   // else 32-bit byte offsets do not reach
+  // bins per lane (vector ALU), or per lane group as 16-bin sub-tiles (matrix cores)
+  const int bins = h->bshape.E == 1 ? 16 : 64;
+  if (h->bshape.E == 1) {
+    TB = 16;   // matrix cores: time groups of 16, 16 bins per wave
+    V = 1;
+  } else {
+    if (TB == 16 && bc.vec == 0) V = 1;
+    if (TB == 16 && V != 1) TB = 8;
+  }
   h->b_tb = TB;
-  while (64 * V > N && V > 1) V /= 2;
+  while (bins * V > N && V > 1) V /= 2;
   int NW = bc.waves > 0 ? bc.waves : 4;
   NW = NW >= 4 ? 4 : (NW >= 2 ? 2 : 1);
-  while (64 * V * NW > N && NW > 1) NW /= 2;
+  while (bins * V * NW > N && NW > 1) NW /= 2;
   h->bshape.V = V;
   h->bshape.NW = NW;
-  h->b_tile_width = (engine == 2 ? 16 : 64 * V) * NW;   // matrix cores: 16 bins per wave
+  h->b_tile_width = bins * V * NW;
   const int T = N / h->b_tile_width;
 
   std::vector<std::vector<int>> by_input(h->I);
@@ -552,8 +577,20 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   }
   h->fdl_elems = off;
 
-  HIP_TRY(h, dalloc(&h->d_bank, (size_t)h->bank_elems * h->store_bytes));
-  HIP_TRY(h, dalloc(&h->d_fdl, (size_t)h->fdl_elems * h->store_bytes));
+  // zero rows after the last channel: the matrix-core MAC loads partition rows
+  // up to 16 ahead of the one it multiplies, and a channel shorter than the
+  // other channel of its item up to the other's partition count (the values
+  // are masked; the addresses must stay inside the allocation)
+  {
+    int maxM = 1;
+    for (int c = 0; c < h->C; ++c) maxM = std::max(maxM, h->ch_M[c]);
+    h->bank_pad_rows = maxM + 32;
+  }
+  // one allocation holds the bank (with its padding) and then the delay line,
+  // so one base and 32-bit offsets reach both
+  h->bank_alloc_bytes = (((size_t)(h->bank_elems + (int64_t)h->bank_pad_rows * N) * h->store_bytes + 255) / 256) * 256;
+  HIP_TRY(h, dalloc(&h->d_bank, h->bank_alloc_bytes + (size_t)h->fdl_elems * h->store_bytes));
+  h->d_fdl = static_cast<char*>(h->d_bank) + h->bank_alloc_bytes;
   HIP_TRY(h, dalloc(&h->d_hist, (size_t)2 * h->I * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_ola, (size_t)h->n_out * 3 * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_out_ptr, (size_t)(h->n_out + 1) * sizeof(int32_t)));
@@ -620,7 +657,8 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   HIP_TRY(h, hipMemcpy(h->d_in_M, h->in_M.data(), h->I * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_in_fdl_off, h->in_fdl_off.data(), h->I * sizeof(int64_t), hipMemcpyHostToDevice));
 
-  HIP_TRY(h, hipMemsetAsync(h->d_bank, 0, (size_t)h->bank_elems * h->store_bytes, h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->d_bank, 0, (size_t)(h->bank_elems + (int64_t)h->bank_pad_rows * N) * h->store_bytes,
+                            h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_fdl, 0, (size_t)h->fdl_elems * h->store_bytes, h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_hist, 0, (size_t)2 * h->I * L * sizeof(float), h->stream));
   HIP_TRY(h, hipMemsetAsync(h->d_ola, 0, (size_t)h->n_out * 3 * L * sizeof(float), h->stream));
@@ -1050,11 +1088,11 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
   for (int grp : groups)
   for (int tb : tbs)
   for (int vec : vecs) {
-    if (tb == 16 && vec != 1) continue;
+    if (eng == 1 && tb == 16 && vec != 1) continue;
     if (eng == 2 && (tb != 16 || vec != 1)) continue;
     const int tgroups = 2 * (((nb + 1) / 2 + tb - 1) / tb);
     for (int nw : {1, 2, 4}) {
-      const int tw = (eng == 2 ? 16 : 64 * vec) * nw;
+      const int tw = (eng == 2 ? 16 : 64) * vec * nw;
       if (tw > N) continue;
       const int tiles = N / tw;
       std::vector<int> chunks;

@@ -20,6 +20,7 @@
 
 #include <type_traits>
 #include <utility>
+#include <numeric>
 
 #include "fft_lds.hpp"
 #include "tvolap_internal.h"
@@ -981,16 +982,27 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
 // Even and odd pairs may take different slots (a stream that switches every
 // block alternates two slots in a parity class); other slot patterns run
 // passes in which the blocks of other slots are masked out of the A operand.
-// A wave covers 16 U bins (U sub-tiles of 16); PD partitions are loaded ahead.
-template <int L, int U, int PD, int DT>
+// A wave covers 16 bins; its operands are fetched PG partitions ahead with
+// 16-byte loads and passed through LDS (see the staging comment).
+template <int L, int PG, int DT>
 __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
   static_assert(DT == 0, "matrix-core MAC: f32 spectra");
-  static_assert(U == 1 || U == 2 || U == 4, "sub-tiles per wave");
-  static_assert(PD == 2 || PD == 4 || PD == 8, "prefetch depth divides the window");
   typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int U = 1;                      // 16 bins per wave
   constexpr int TB = 16;
   constexpr int N = 2 * L;
-  constexpr int RS = 2 * N;                 // floats per delay-line / partition row
+  constexpr uint32_t RB = 8u * N;           // bytes per delay-line / partition row
+  constexpr int R = PG;                     // delay-line window registers per lane (9 in use)
+  constexpr int LS = 4;                     // staging slots per wave
+  constexpr int PER = std::lcm(R, LS);      // unroll period (static register indices)
+  static_assert(PG >= 9 && PER % PG == 0, "window and load ring");
+  // Staging: per step a wave needs two delay-line row pieces and four
+  // partition-spectrum row pieces of 128 B (its 16 bins); 48 lanes fetch them
+  // with one 16-byte load each (lanes 48..63 repeat delay-line pieces), the
+  // wave writes them to its slot and every lane reads its own three operands
+  // back. The bank and the delay line share one allocation, so every lane
+  // addresses its piece with a 32-bit offset from the bank.
+  __shared__ f4 stage[4][LS][64];
   const int TW = B.tile_width;              // 16 U bins per wave
   const DevPlan& P = B.P;
   const int lane = threadIdx.x & 63;
@@ -1005,8 +1017,8 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
   const int pairs = 2 * B.n_mac;
   const int lanes8 = (pairs + 7) / 8;
   const int total = 8 * lanes8 * groups;
-  const float* bank = static_cast<const float*>(B.bank);
-  const float* fdl = static_cast<const float*>(B.fdl);
+  const char* bank = static_cast<const char*>(B.bank);
+  const char* fdl = static_cast<const char*>(B.fdl);
   for (int idx = blockIdx.x; idx < total; idx += gridDim.x) {
     const int x = idx & 7, y = idx >> 3;
     const int gi = y % groups;
@@ -1025,7 +1037,10 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
     const int p = (int)(c0 & 1u);
     const int qh = hh ? ring_slot(c0 + 16u, Mi) : ring_slot(c0, Mi);   // ring slot of block 8 hh
     const uint32_t f0 = 2u * (uint32_t)(it.tile * TW + w * 16 * U + b16) + (uint32_t)comp;   // float in a row
-    const float* xb = fdl + 2 * (P.in_fdl_off[i] + (int64_t)p * Mi * N);
+    const uint32_t lane_bytes = 4u * f0;
+    // delay line of input i, parity p: Mi rows from a uniform base
+    const char* xb = fdl + 8 * (P.in_fdl_off[i] + (int64_t)p * Mi * N);
+    const uint32_t ring_bytes = (uint32_t)Mi * RB;
     int ch[2], McL[2], Mc[2];
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
@@ -1045,11 +1060,14 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
         const int sv = uniform(slot[g][b]);
         slot[g][b] = sv < 0 ? 0 : (sv >= P.K ? P.K - 1 : sv);
       }
-    // the lane's channel (B operand) and its partition range
+    // partition spectra: a uniform base at channel ch[0] and 32-bit byte
+    // offsets (the channels of an item are in increasing bank order; the
+    // host keeps the span below 2^32 and pads the bank with zero rows, which
+    // the loads ahead of the last partition may reach)
+    const char* hb = bank + 8 * P.ch_bank_off[ch[0]];
+    const uint32_t ch_bytes = hh ? (uint32_t)(8 * (P.ch_bank_off[ch[1]] - P.ch_bank_off[ch[0]])) : 0u;
+    const uint32_t slot_bytes = (uint32_t)(hh ? McL[1] : McL[0]) * RB;
     const int Mcl = hh ? Mc[1] : Mc[0];
-    const int mlast = min(m1, hh ? McL[1] : McL[0]) - 1;
-    const float* hch = bank + 2 * (hh ? P.ch_bank_off[ch[1]] : P.ch_bank_off[ch[0]]);
-    const int64_t slot_stride = (int64_t)(hh ? McL[1] : McL[0]) * RS;
 
     f4 acc[8][U];
 #pragma unroll
@@ -1057,71 +1075,92 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
 #pragma unroll
       for (int u = 0; u < U; ++u) acc[q][u] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // One pass over the partitions [m0, m1). Even pairs take the spectra at
-    // he, odd pairs those at ho; rows of blocks outside `act` are masked out
-    // of the A operand. (A single code path: variants of it would each hold
-    // their own copy of the accumulators.)
-    auto run = [&](const float* he, const float* ho, uint32_t act) {
-      constexpr int ND = 2;
-      // Delay-line values by d = q - s (pair q at step s = mm - m0), in a
-      // circular buffer of R = 8 + PD registers per bin: d = 7 - s .. -s are
-      // in use at step s, d = -s - 1 .. -s - PD are in flight, and the load
-      // for d = -s - 1 - PD reuses the register of d = 7 - s after step s.
-      constexpr int R = 8 + PD;
-      float W[R][U];
-      auto load_x = [&](float (&o)[U], int d) {   // X of block 8 hh + d at partition m0
-        int r = (qh + d - m0) % Mi;
+    auto ldf = [](const char* base, uint32_t off) { return *reinterpret_cast<const float*>(base + off); };
+    // loader role of lanes 0..47: part 0, 1: delay-line row of block 8 part;
+    // part 2 + 2 d + g: partition spectrum of channel g, slot set d (even, odd)
+    const int part = lane < 48 ? (lane >> 3) : ((lane >> 3) - 6), within = lane & 7;
+    const uint32_t tile_bytes = (uint32_t)(it.tile * TW + w * 16) * 8u;
+    const int gq = ring_slot(c0 + (part == 1 ? 16u : 0u), Mi);   // loader's ring slot of block 8 part
+    const int lg = part & 1;                                     // loader's channel (H parts)
+    const uint32_t lch_bytes = lg ? (uint32_t)(8 * (P.ch_bank_off[ch[1]] - P.ch_bank_off[ch[0]])) : 0u;
+    const uint32_t lslot_bytes = (uint32_t)(lg ? McL[1] : McL[0]) * RB;
+    f4* st = stage[w][0];
+    const uint32_t xbo = (uint32_t)(xb - bank);    // delay line of (input, parity) from the bank base
+    const float* stf = reinterpret_cast<const float*>(stage[w][0]);
+    const int rx = 32 * hh + 2 * b16 + comp;   // reader's float in a slot: X; He at +64, Ho at +128
+
+    // One pass over the partitions [m0, m1). Even pairs take the spectra of
+    // slots se, odd pairs those of so; rows of blocks outside `act` are
+    // masked out of the A operand. (A single code path: variants of it would
+    // each hold their own copy of the accumulators.)
+    auto run = [&](const int (&se)[2], const int (&so)[2], uint32_t act) {
+      // Delay-line values by d = q - s (pair q at step s = mm - m0) in a
+      // circular buffer of R registers: d = 7 - s .. -s are in use at step s
+      // and d = -s - 1 is read from the staging slot during step s.
+      float W[R];
+      float Bq[2][2];
+      f4 G[PG];                                // row-step k (d = -k, partition m0 + k) in G[k mod PG]
+      const uint32_t he = ch_bytes + (uint32_t)(hh ? se[1] : se[0]) * slot_bytes + lane_bytes;
+      const uint32_t ho = ch_bytes + (uint32_t)(hh ? so[1] : so[0]) * slot_bytes + lane_bytes;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int r = (qh + q - m0) % Mi;
         r = r < 0 ? r + Mi : r;
-        const float* src = xb + (uint32_t)r * RS + f0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) o[u] = src[32 * u];
-      };
-      auto load_xs = [&](float (&o)[U], int s) {  // d = -s (pair 0 at step s), s >= 1
-        int r = qh - min(m0 + s, m1 - 1);
-        r = r < 0 ? r + Mi : r;
-        const float* src = xb + (uint32_t)r * RS + f0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) o[u] = src[32 * u];
-      };
-      float Hq[PD][ND][U];
-      auto load_h = [&](float (&o)[ND][U], int mm) {
-        const uint32_t off = (uint32_t)min(mm, mlast) * RS + f0;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          const float* src = (d == 0 ? he : ho) + off;
-#pragma unroll
-          for (int u = 0; u < U; ++u) o[d][u] = src[32 * u];
-        }
-      };
-#pragma unroll
-      for (int q = 0; q < 8; ++q) load_x(W[q], q);
-#pragma unroll
-      for (int k = 0; k < PD; ++k) {
-        load_h(Hq[k], m0 + k);
-        load_xs(W[R - 1 - k], k + 1);   // d = -(k + 1)
+        W[q] = ldf(xb, (uint32_t)r * RB + lane_bytes);
       }
-      // step s (S = s mod R, s = mm - m0)
-      auto advance = [&](int mm, auto sc) {
-        constexpr int S = decltype(sc)::value;
-        const bool on = mm < Mcl;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          float bq[ND];
-#pragma unroll
-          for (int d = 0; d < ND; ++d) bq[d] = on ? Hq[S % PD][d][u] : 0.f;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            float a = W[(((q - S) % R) + R) % R][u];
-            a = ((act >> (q + 8 * hh)) & 1u) ? a : 0.f;
-            acc[q][u] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, bq[q & 1], acc[q][u], 0, 0, 0);
-          }
-        }
-        load_h(Hq[S % PD], mm + PD);
-        load_xs(W[(((7 - S) % R) + R) % R], mm - m0 + 1 + PD);
+      Bq[0][0] = ldf(hb, he + (uint32_t)m0 * RB);
+      Bq[0][1] = ldf(hb, ho + (uint32_t)m0 * RB);
+      // loader address of row-step k
+      const int lslot = part < 2 ? 0 : ((part >> 1) == 1 ? (lg ? se[1] : se[0]) : (lg ? so[1] : so[0]));
+      const uint32_t lh = lch_bytes + (uint32_t)lslot * lslot_bytes + tile_bytes + 16u * (uint32_t)within;
+      // loader's running byte offset from the bank base for row-steps 1, 2,
+      // ...: delay-line rows go down the ring (wrapping at lo), partition
+      // rows up the bank
+      const bool xl = part < 2;
+      const uint32_t lo = xl ? xbo + tile_bytes + 16u * (uint32_t)within : 0u;   // ring row 0
+      const uint32_t wrap = xl ? ring_bytes : 0u;
+      const uint32_t dl = xl ? (uint32_t)(-(int32_t)RB) : RB;
+      uint32_t goff;
+      {
+        int r = (gq - m0 - 1) % Mi;
+        r = r < 0 ? r + Mi : r;
+        goff = xl ? lo + (uint32_t)r * RB : (uint32_t)(hb - bank) + lh + (uint32_t)(m0 + 1) * RB;
+      }
+      auto gload = [&](f4& o) {                // the next row-step
+        o = *reinterpret_cast<const f4*>(bank + goff);
+        goff += dl;
+        goff += goff < lo ? wrap : 0u;
       };
+#pragma unroll
+      for (int k = 1; k <= PG; ++k) gload(G[k % PG]);
+      st[1 * 64 + lane] = G[1];
+      gload(G[1]);                             // row-step 1 + PG
+      auto advance = [&](int mm, auto sc) {
+        constexpr int S = decltype(sc)::value;   // step index mod PER
+        // a. operands of row-step s + 1 from its staging slot
+        {
+          const float* sl = stf + ((S + 1) % LS) * 256;
+          W[(((-S - 1) % R) + R) % R] = sl[rx];
+          const bool on1 = mm + 1 < Mcl;
+          const float e = sl[64 + rx], o = sl[128 + rx];
+          Bq[(S + 1) & 1][0] = on1 ? e : 0.f;
+          Bq[(S + 1) & 1][1] = on1 ? o : 0.f;
+        }
+        // b. the products of step s
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          float a = W[(((q - S) % R) + R) % R];
+          a = ((act >> (q + 8 * hh)) & 1u) ? a : 0.f;
+          acc[q][0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, Bq[S & 1][q & 1], acc[q][0], 0, 0, 0);
+        }
+        // c. stage row-step s + 2; d. fetch row-step s + 2 + PG
+        st[((S + 2) % LS) * 64 + lane] = G[(S + 2) % PG];
+        gload(G[(S + 2) % PG]);
+      };
+      if (!(m0 < Mcl)) { Bq[0][0] = 0.f; Bq[0][1] = 0.f; }
       int mb = m0;
-      for (; mb + R <= m1; mb += R) static_for<R>([&](auto sc) { advance(mb + decltype(sc)::value, sc); });
-      static_for<R>([&](auto sc) {
+      for (; mb + PER <= m1; mb += PER) static_for<PER>([&](auto sc) { advance(mb + decltype(sc)::value, sc); });
+      static_for<PER>([&](auto sc) {
         if (mb + decltype(sc)::value < m1) advance(mb + decltype(sc)::value, sc);
       });
     };
@@ -1157,8 +1196,7 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
           act |= 1u << b;
       }
       todo &= ~act;
-      run(hch + (hh ? se[1] : se[0]) * slot_stride, hch + (hh ? so[1] : so[0]) * slot_stride,
-          act | ~all);
+      run(se, so, act | ~all);
     }
 
     // Re Y = ReX ReH - ImX ImH (Re lane), Im Y = ReX ImH + ImX ReH (Im lane);
@@ -1675,7 +1713,7 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
           if (shape.G > 2 || B.time_block != 16 || shape.V != 1) return hipErrorInvalidValue;
           if (shape.NW != 1 && shape.NW != 2 && shape.NW != 4) return hipErrorInvalidValue;
           if (16 * shape.NW != B.tile_width || B.tile_width > 2 * L) return hipErrorInvalidValue;
-          hipLaunchKernelGGL((k_tmfma<L, 1, 4, DT>), dim3(grid), dim3(64 * shape.NW), 0, s, B);
+          hipLaunchKernelGGL((k_tmfma<L, 12, DT>), dim3(grid), dim3(64 * shape.NW), 0, s, B);
           e = hipGetLastError();
         } else {
           return hipErrorInvalidValue;

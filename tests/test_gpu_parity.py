@@ -472,20 +472,20 @@ def test_matrix_core_engine_matches_single_blocks_and_oracle(case, batch):
     assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
 
 
-# (chunk, waves, group) of the matrix-core engine
-MFMA_SCHEDULES = [(0, 0, 0), (2, 1, 1), (3, 2, 2), (1, 4, 1), (200, 1, 2), (5, 2, 1)]
+# (chunk, vec, waves, group) of the matrix-core engine
+MFMA_SCHEDULES = [(0, 0, 0, 0), (2, 1, 1, 1), (3, 0, 2, 2), (1, 1, 4, 1), (200, 1, 1, 2), (5, 0, 4, 1)]
 
 
-@pytest.mark.parametrize("sched", MFMA_SCHEDULES, ids=[f"c{s[0]}w{s[1]}g{s[2]}" for s in MFMA_SCHEDULES])
+@pytest.mark.parametrize("sched", MFMA_SCHEDULES, ids=[f"c{s[0]}v{s[1]}w{s[2]}g{s[3]}" for s in MFMA_SCHEDULES])
 @pytest.mark.parametrize("case", [SMALL_CASES[1], SMALL_CASES[4], SMALL_CASES[3]], ids=["s2_L128", "s5_L64", "s4_L512"])
 def test_matrix_core_engine_schedules(case, sched):
     seed, L, C, I, N, tr, K, p = case
-    chunk, waves, group = sched
+    chunk, vec, waves, group = sched
     log(f"matrix-core schedule {sched} case {case}")
     wl = synth.random_small(seed=seed + 100, hop=L, n_channels=C, n_inputs=I, n_samples=N,
                             taps_range=tr, n_slots=K, p_switch=p)
     conv = make_convolver(wl, max_batch=32)
-    conv.configure_batch(chunk=chunk, waves=waves, group=group, engine=2)
+    conv.configure_batch(chunk=chunk, vec=vec, waves=waves, group=group, engine=2)
     got = gpu_streams(wl, conv=conv, batch=11)
     conv.close()
     assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
