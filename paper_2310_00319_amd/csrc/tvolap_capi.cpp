@@ -130,6 +130,7 @@ struct tvolap {
   int32_t* d_brow_base = nullptr;
   int32_t* d_bnchunks = nullptr;
   float2* d_bypart = nullptr;     // [max_batch][n_brows][b_tile_width]
+  int32_t* d_defer = nullptr;     // [1 + units]: count, then units the matrix-core MAC defers
   float* d_yblk = nullptr;        // [max_batch][C][4L]
   int32_t* d_tune_bsel = nullptr; // [max_batch][C] autotuner schedule (slot = block mod K)
 
@@ -217,6 +218,7 @@ void free_batch_work(tvolap_t* h) {
   dfree(h->d_brow_base);
   dfree(h->d_bnchunks);
   dfree(h->d_bypart);
+  dfree(h->d_defer);
 }
 
 void free_all(tvolap_t* h) {
@@ -377,7 +379,7 @@ void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   // bins per lane (vector ALU), or per lane group as 16-bin sub-tiles (matrix cores)
   const int bins = h->bshape.E == 1 ? 16 : 64;
   if (h->bshape.E == 1) {
-    TB = 16;   // matrix cores: time groups of 16, 16 bins per wave
+    TB = 16;   // matrix cores: time groups of 16, 16 bins per wave, 4 waves
     V = 1;
   } else {
     if (TB == 16 && bc.vec == 0) V = 1;
@@ -387,6 +389,7 @@ void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   while (bins * V > N && V > 1) V /= 2;
   int NW = bc.waves > 0 ? bc.waves : 4;
   NW = NW >= 4 ? 4 : (NW >= 2 ? 2 : 1);
+  if (h->bshape.E == 1) NW = 4;   // 64-bin tiles, which the vector-ALU MAC of deferred units also takes
   while (bins * V * NW > N && NW > 1) NW /= 2;
   h->bshape.V = V;
   h->bshape.NW = NW;
@@ -484,6 +487,13 @@ int upload_batch_work(tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_brow_base, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_bnchunks, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_bypart, (size_t)h->max_batch * h->n_brows * h->b_tile_width * sizeof(float2)));
+  {
+    // work units of a full call: 8-aligned (item, class) pairs times time groups
+    const int64_t groups = ((h->max_batch + 1) / 2 + h->b_tb - 1) / h->b_tb;
+    const int64_t units = 8 * (int64_t)((2 * h->n_bmac + 7) / 8) * groups;
+    HIP_TRY(h, dalloc(&h->d_defer, (size_t)(1 + units) * sizeof(int32_t)));
+    HIP_TRY(h, hipMemset(h->d_defer, 0, sizeof(int32_t)));
+  }
   HIP_TRY(h, hipMemcpy(h->d_bitems, h->bitems.data(), h->bitems.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_brow_base, h->b_row_base.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(h, hipMemcpy(h->d_bnchunks, h->b_nchunks.data(), h->C * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -966,6 +976,9 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   B.done = h->d_done;
   B.counter = h->d_counter;
   B.bus_rows = h->mixdown ? 1 : 0;
+  B.defer_count = h->d_defer;
+  B.defer_list = h->d_defer + 1;
+  B.from_list = 0;
   const int groups = ((n_blocks + 1) / 2 + h->b_tb - 1) / h->b_tb;
   const int grid = 8 * ((2 * h->n_bmac + 7) / 8) * groups;   // k_tmac's XCD-aware index space
   TimingSet* ts = nullptr;

@@ -111,6 +111,11 @@ struct BatchArgs {
   int32_t* done;
   uint64_t* counter;
   int32_t bus_rows;            // 1: mixdown; bus sums are formed in the partial rows before the inverse
+  // Work units (time groups of an item) that the matrix-core MAC leaves to
+  // the vector-ALU MAC: irregular slot patterns and ragged channel pairs.
+  int32_t* defer_list;         // [units]
+  int32_t* defer_count;        // [1], zeroed by the spectra kernel of each call
+  int32_t from_list;           // k_tmac: process defer_list[0 .. *defer_count)
 };
 // ev (may be NULL): four events recorded before the spectra, before the MAC,
 // after the MAC and after the overlap-add.

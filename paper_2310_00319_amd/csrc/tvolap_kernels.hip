@@ -536,9 +536,12 @@ template <int L, int DT>
 __global__ __launch_bounds__(256) void k_batch_spectra(DevPlan P, const float* __restrict__ in, int64_t in_stride,
                                                        const float* __restrict__ hist,
                                                        typename Store<DT>::T* __restrict__ fdl,
-                                                       const uint64_t* __restrict__ counter, int n_blocks) {
+                                                       const uint64_t* __restrict__ counter, int n_blocks,
+                                                       int32_t* __restrict__ defer_count) {
   constexpr int N = 2 * L;
   constexpr int T = 256;
+  // the matrix-core MAC of this call appends to an empty deferred list
+  if (defer_count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *defer_count = 0;
   __shared__ float2 twl[2 * N];
   __shared__ float winl[N];
   __shared__ float2 bufA[N];
@@ -623,7 +626,10 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
   const int total = 8 * lanes8 * groups;
   const ST* bank = static_cast<const ST*>(B.bank);
   const ST* fdl = static_cast<const ST*>(B.fdl);
-  for (int idx = blockIdx.x; idx < total; idx += gridDim.x) {
+  // from_list: the units the matrix-core MAC deferred (index space as below)
+  const int n_units = B.from_list ? *B.defer_count : total;
+  for (int u = blockIdx.x; u < n_units; u += gridDim.x) {
+    const int idx = B.from_list ? B.defer_list[u] : u;
     const int x = idx & 7, y = idx >> 3;
     const int gi = y % groups;
     const int pr = x + 8 * (y / groups);               // (item, class) pair
@@ -1067,7 +1073,6 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
     const char* hb = bank + 8 * P.ch_bank_off[ch[0]];
     const uint32_t ch_bytes = hh ? (uint32_t)(8 * (P.ch_bank_off[ch[1]] - P.ch_bank_off[ch[0]])) : 0u;
     const uint32_t slot_bytes = (uint32_t)(hh ? McL[1] : McL[0]) * RB;
-    const int Mcl = hh ? Mc[1] : Mc[0];
 
     f4 acc[8][U];
 #pragma unroll
@@ -1089,11 +1094,9 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
     const float* stf = reinterpret_cast<const float*>(stage[w][0]);
     const int rx = 32 * hh + 2 * b16 + comp;   // reader's float in a slot: X; He at +64, Ho at +128
 
-    // One pass over the partitions [m0, m1). Even pairs take the spectra of
-    // slots se, odd pairs those of so; rows of blocks outside `act` are
-    // masked out of the A operand. (A single code path: variants of it would
-    // each hold their own copy of the accumulators.)
-    auto run = [&](const int (&se)[2], const int (&so)[2], uint32_t act) {
+    // The partitions [m0, m1): even pairs take the spectra of slots se, odd
+    // pairs those of so.
+    auto run = [&](const int (&se)[2], const int (&so)[2]) {
       // Delay-line values by d = q - s (pair q at step s = mm - m0) in a
       // circular buffer of R registers: d = 7 - s .. -s are in use at step s
       // and d = -s - 1 is read from the staging slot during step s.
@@ -1135,69 +1138,52 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
       for (int k = 1; k <= PG; ++k) gload(G[k % PG]);
       st[1 * 64 + lane] = G[1];
       gload(G[1]);                             // row-step 1 + PG
-      auto advance = [&](int mm, auto sc) {
+      auto advance = [&](auto sc) {
         constexpr int S = decltype(sc)::value;   // step index mod PER
         // a. operands of row-step s + 1 from its staging slot
         {
           const float* sl = stf + ((S + 1) % LS) * 256;
           W[(((-S - 1) % R) + R) % R] = sl[rx];
-          const bool on1 = mm + 1 < Mcl;
-          const float e = sl[64 + rx], o = sl[128 + rx];
-          Bq[(S + 1) & 1][0] = on1 ? e : 0.f;
-          Bq[(S + 1) & 1][1] = on1 ? o : 0.f;
+          Bq[(S + 1) & 1][0] = sl[64 + rx];
+          Bq[(S + 1) & 1][1] = sl[128 + rx];
         }
         // b. the products of step s
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          float a = W[(((q - S) % R) + R) % R];
-          a = ((act >> (q + 8 * hh)) & 1u) ? a : 0.f;
-          acc[q][0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, Bq[S & 1][q & 1], acc[q][0], 0, 0, 0);
-        }
+        for (int q = 0; q < 8; ++q)
+          acc[q][0] = __builtin_amdgcn_mfma_f32_4x4x1f32(W[(((q - S) % R) + R) % R], Bq[S & 1][q & 1], acc[q][0], 0,
+                                                         0, 0);
         // c. stage row-step s + 2; d. fetch row-step s + 2 + PG
         st[((S + 2) % LS) * 64 + lane] = G[(S + 2) % PG];
         gload(G[(S + 2) % PG]);
       };
-      if (!(m0 < Mcl)) { Bq[0][0] = 0.f; Bq[0][1] = 0.f; }
       int mb = m0;
-      for (; mb + PER <= m1; mb += PER) static_for<PER>([&](auto sc) { advance(mb + decltype(sc)::value, sc); });
+      for (; mb + PER <= m1; mb += PER) static_for<PER>([&](auto sc) { advance(sc); });
       static_for<PER>([&](auto sc) {
-        if (mb + decltype(sc)::value < m1) advance(mb + decltype(sc)::value, sc);
+        if (mb + decltype(sc)::value < m1) advance(sc);
       });
     };
 
-    // passes: the even pairs take the slots of the first even block not yet
-    // done, the odd pairs those of the first odd one; blocks with other slots
-    // wait for a later pass
-    const uint32_t all = (1u << nb) - 1u;
-    uint32_t todo = all;
-    while (todo != 0u) {
-      int te = -1, to = -1;
+    // Regular units: every even block of the group takes the slots of block
+    // 0, every odd block those of block 1 (a stream switching every block, or
+    // never), and both channels reach m1. Others go to the deferred list,
+    // which the vector-ALU MAC processes after this kernel.
+    int se[2], so[2];
 #pragma unroll
-      for (int b = TB - 1; b >= 0; --b)
-        if ((todo >> b) & 1u) {
-          if (b & 1) to = b;
-          else te = b;
-        }
-      if (te < 0) te = to;
-      if (to < 0) to = te;
-      int se[2] = {0, 0}, so[2] = {0, 0};
-#pragma unroll
-      for (int b = 0; b < TB; ++b)
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-          if (b == te) se[g] = slot[g][b];
-          if (b == to) so[g] = slot[g][b];
-        }
-      uint32_t act = 0u;
-#pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        const bool ev = (b & 1) == 0;
-        if (((todo >> b) & 1u) && slot[0][b] == (ev ? se[0] : so[0]) && slot[1][b] == (ev ? se[1] : so[1]))
-          act |= 1u << b;
-      }
-      todo &= ~act;
-      run(se, so, act | ~all);
+    for (int g = 0; g < 2; ++g) {
+      se[g] = slot[g][0];
+      so[g] = slot[g][nb > 1 ? 1 : 0];
     }
+    bool regular = m1 <= Mc[0] && (n_ch < 2 || m1 <= Mc[1]);
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (b < nb) regular = regular && slot[g][b] == ((b & 1) ? so[g] : se[g]);
+    if (!regular) {
+      if (threadIdx.x == 0) B.defer_list[atomicAdd(B.defer_count, 1)] = idx;
+      continue;
+    }
+    run(se, so);
 
     // Re Y = ReX ReH - ImX ImH (Re lane), Im Y = ReX ImH + ImX ReH (Im lane);
     // the packed DC / Nyquist bin takes ReX ReH and ImX ImH
@@ -1702,7 +1688,7 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     const int bgroups = (B.n_blocks + kBatchBlocksPerWg - 1) / kBatchBlocksPerWg;
     hipLaunchKernelGGL((k_batch_spectra<L, DT>), dim3(bgroups, B.P.I), dim3(256), 0, s, B.P, in, in_stride, hist,
-                       static_cast<ST*>(B.fdl), B.counter, B.n_blocks);
+                       static_cast<ST*>(B.fdl), B.counter, B.n_blocks, B.defer_count);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
@@ -1710,10 +1696,19 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
       if (shape.E == 1) {
         // matrix-core MAC: f32 spectra, up to two channels per item, time groups of 16
         if constexpr (DT == 0) {
-          if (shape.G > 2 || B.time_block != 16 || shape.V != 1) return hipErrorInvalidValue;
-          if (shape.NW != 1 && shape.NW != 2 && shape.NW != 4) return hipErrorInvalidValue;
-          if (16 * shape.NW != B.tile_width || B.tile_width > 2 * L) return hipErrorInvalidValue;
-          hipLaunchKernelGGL((k_tmfma<L, 12, DT>), dim3(grid), dim3(64 * shape.NW), 0, s, B);
+          if (shape.G > 2 || B.time_block != 16 || shape.V != 1 || shape.NW != 4) return hipErrorInvalidValue;
+          if (B.tile_width != 64 || B.tile_width > 2 * L || !B.defer_list || !B.defer_count)
+            return hipErrorInvalidValue;
+          hipLaunchKernelGGL((k_tmfma<L, 12, DT>), dim3(grid), dim3(256), 0, s, B);
+          e = hipGetLastError();
+          if (e != hipSuccess) return e;
+          // the deferred units on the vector ALU: one wave per 64-bin tile
+          BatchArgs Bd = B;
+          Bd.from_list = 1;
+          if (shape.G == 1)
+            hipLaunchKernelGGL((k_tmac<L, 1, 1, 16, DT>), dim3(grid), dim3(64), 0, s, Bd);
+          else
+            hipLaunchKernelGGL((k_tmac<L, 1, 2, 16, DT>), dim3(grid), dim3(64), 0, s, Bd);
           e = hipGetLastError();
         } else {
           return hipErrorInvalidValue;
