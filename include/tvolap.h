@@ -228,14 +228,17 @@ int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us);
  * partition spectra. chunk: partitions per work item (0 = about one workgroup
  * per compute unit); vec: complex bins per lane (1 or 2; 0 = 2, or 1 with time
  * groups of 16); waves: 1, 2 or 4 waves per workgroup, each owning 64 vec bins
- * (0 = 4, fewer when 2L bins are fewer); time_block: 8 or 16 (16 needs vec 1;
- * 0 = 16 when max_batch >= 32, else 8); group: channels of one input per work
- * item, 1 or 2 (two channels share the delay-line loads; 0 = 2 when an input
+ * (0 = 4, fewer when 2L bins are fewer; the matrix-core engine takes 4 or 8
+ * waves of 16 bins); time_block: 8, 16 or 32 (16 needs vec 1, 32 the
+ * matrix-core engine; 0 = 16 when max_batch >= 32, else 8); group: channels
+ * of one input per work item, 1 or 2 (two channels share the delay-line loads; 0 = 2 when an input
  * feeds several channels); engine: 1 = vector ALU (multiply-adds or packed
  * dot products per complex product), 2 = matrix cores (f32 spectra only: per
  * bin, the products of a time group of 16 blocks and the two channels of an
- * input are 4x4 outer products, one 16-bin MFMA each; implies time groups of
- * 16 and 16 bins per wave, so vec must be 0 or 1), 0 = 1. Waits for the stream; rebuilds the
+ * input are 4x4 outer products, one 16-bin MFMA each; 16 bins per wave, so vec
+ * must be 0 or 1; time groups of 16 or 32 blocks, 0 = 32 when max_batch >= 64;
+ * time groups whose slots do not alternate by parity go to the vector ALU),
+ * 0 = 1. Waits for the stream; rebuilds the
  * batched work list. Errors: EINVAL (also engine 2 with 16-bit spectra),
  * ESTATE during capture, ENOMEM/EDEVICE. */
 int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block,

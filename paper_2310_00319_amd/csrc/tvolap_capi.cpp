@@ -379,7 +379,8 @@ void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   // bins per lane (vector ALU), or per lane group as 16-bin sub-tiles (matrix cores)
   const int bins = h->bshape.E == 1 ? 16 : 64;
   if (h->bshape.E == 1) {
-    TB = 16;   // matrix cores: time groups of 16, 16 bins per wave, 4 waves
+    // matrix cores: time groups of 16 or 32 blocks, 16 bins per wave, 4 waves
+    TB = bc.time_block == 16 ? 16 : (bc.time_block == 32 || h->max_batch >= 64 ? 32 : 16);
     V = 1;
   } else {
     if (TB == 16 && bc.vec == 0) V = 1;
@@ -389,7 +390,9 @@ void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   while (bins * V > N && V > 1) V /= 2;
   int NW = bc.waves > 0 ? bc.waves : 4;
   NW = NW >= 4 ? 4 : (NW >= 2 ? 2 : 1);
-  if (h->bshape.E == 1) NW = 4;   // 64-bin tiles, which the vector-ALU MAC of deferred units also takes
+  // matrix cores: 4 or 8 waves (tiles of 64 or 128 bins, which the vector-ALU
+  // MAC of deferred units takes with 1 or 2 waves)
+  if (h->bshape.E == 1) NW = (bc.waves == 8 && N >= 128) ? 8 : 4;
   while (bins * V * NW > N && NW > 1) NW /= 2;
   h->bshape.V = V;
   h->bshape.NW = NW;
@@ -489,7 +492,8 @@ int upload_batch_work(tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_bypart, (size_t)h->max_batch * h->n_brows * h->b_tile_width * sizeof(float2)));
   {
     // work units of a full call: 8-aligned (item, class) pairs times time groups
-    const int64_t groups = ((h->max_batch + 1) / 2 + h->b_tb - 1) / h->b_tb;
+    // (in the vector-ALU MAC's index space: time groups of 16)
+    const int64_t groups = ((h->max_batch + 1) / 2 + 15) / 16;
     const int64_t units = 8 * (int64_t)((2 * h->n_bmac + 7) / 8) * groups;
     HIP_TRY(h, dalloc(&h->d_defer, (size_t)(1 + units) * sizeof(int32_t)));
     HIP_TRY(h, hipMemset(h->d_defer, 0, sizeof(int32_t)));
@@ -1021,9 +1025,11 @@ int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t wave
   if (h->capturing) return fail(h, TVOLAP_ESTATE, "cannot reconfigure during graph capture");
   if (chunk < 0) return fail(h, TVOLAP_EINVAL, "chunk must be >= 0");
   if (vec != 0 && vec != 1 && vec != 2) return fail(h, TVOLAP_EINVAL, "vec must be 0, 1 or 2");
-  if (waves != 0 && waves != 1 && waves != 2 && waves != 4) return fail(h, TVOLAP_EINVAL, "waves must be 0, 1, 2 or 4");
-  if (time_block != 0 && time_block != 8 && time_block != 16)
-    return fail(h, TVOLAP_EINVAL, "time_block must be 0, 8 or 16");
+  if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
+    return fail(h, TVOLAP_EINVAL, "waves must be 0, 1, 2, 4 or 8 (8: matrix cores only)");
+  if (time_block != 0 && time_block != 8 && time_block != 16 && time_block != 32)
+    return fail(h, TVOLAP_EINVAL, "time_block must be 0, 8, 16 or 32");
+  if (time_block == 32 && engine != 2) return fail(h, TVOLAP_EINVAL, "time_block 32 needs the matrix-core engine");
   if (time_block == 16 && vec == 2) return fail(h, TVOLAP_EINVAL, "time_block 16 needs vec 1");
   if (group != 0 && group != 1 && group != 2) return fail(h, TVOLAP_EINVAL, "group must be 0, 1 or 2");
   if (engine < 0 || engine > 2) return fail(h, TVOLAP_EINVAL, "engine must be 0, 1 or 2");
@@ -1065,6 +1071,7 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
   }
   std::vector<int> tbs = {8};
   if (nb >= 32) tbs.push_back(16);
+  if (nb >= 64) tbs.push_back(32);   // matrix cores only
   // zero input and scratch output of one full batch, for the timing only
   float* tin = nullptr;
   float* tout = nullptr;
@@ -1101,10 +1108,11 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
   for (int grp : groups)
   for (int tb : tbs)
   for (int vec : vecs) {
-    if (eng == 1 && tb == 16 && vec != 1) continue;
-    if (eng == 2 && (tb != 16 || vec != 1)) continue;
+    if (eng == 1 && ((tb == 16 && vec != 1) || tb == 32)) continue;
+    if (eng == 2 && (tb == 8 || vec != 1)) continue;
     const int tgroups = 2 * (((nb + 1) / 2 + tb - 1) / tb);
-    for (int nw : {1, 2, 4}) {
+    for (int nw : {1, 2, 4, 8}) {
+      if ((eng == 2) != (nw >= 4)) continue;   // matrix cores: 4 or 8 waves; vector ALU: up to 4
       const int tw = (eng == 2 ? 16 : 64) * vec * nw;
       if (tw > N) continue;
       const int tiles = N / tw;

@@ -990,31 +990,31 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
 // passes in which the blocks of other slots are masked out of the A operand.
 // A wave covers 16 bins; its operands are fetched PG partitions ahead with
 // 16-byte loads and passed through LDS (see the staging comment).
-template <int L, int PG, int DT>
-__global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
+template <int L, int NP, int R, int PG, int NWV, int DT>
+__global__ __launch_bounds__(64 * NWV) void k_tmfma(BatchArgs B) {
   static_assert(DT == 0, "matrix-core MAC: f32 spectra");
+  static_assert(NP == 8 || NP == 16, "pairs per time group");
   typedef float f4 __attribute__((ext_vector_type(4)));
   constexpr int U = 1;                      // 16 bins per wave
-  constexpr int TB = 16;
+  constexpr int TB = 2 * NP;                // blocks of one parity per time group
   constexpr int N = 2 * L;
   constexpr uint32_t RB = 8u * N;           // bytes per delay-line / partition row
-  constexpr int R = PG;                     // delay-line window registers per lane (9 in use)
   constexpr int LS = 4;                     // staging slots per wave
-  constexpr int PER = std::lcm(R, LS);      // unroll period (static register indices)
-  static_assert(PG >= 9 && PER % PG == 0, "window and load ring");
+  constexpr int PER = std::lcm(std::lcm(R, LS), PG);   // unroll period (static register indices)
+  static_assert(R >= NP + 1 && PG >= 3, "window and load ring");
   // Staging: per step a wave needs two delay-line row pieces and four
   // partition-spectrum row pieces of 128 B (its 16 bins); 48 lanes fetch them
   // with one 16-byte load each (lanes 48..63 repeat delay-line pieces), the
   // wave writes them to its slot and every lane reads its own three operands
   // back. The bank and the delay line share one allocation, so every lane
   // addresses its piece with a 32-bit offset from the bank.
-  __shared__ f4 stage[4][LS][64];
+  __shared__ f4 stage[NWV][LS][64];
   const int TW = B.tile_width;              // 16 U bins per wave
   const DevPlan& P = B.P;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int b16 = lane >> 2;                // bin of the lane's MFMA block
-  const int hh = (lane >> 1) & 1;           // A: block half (t = q + 8 hh); B and C: channel
+  const int hh = (lane >> 1) & 1;           // A: block half (t = q + NP hh); B and C: channel
   const int comp = lane & 1;                // Re (0) or Im (1)
   const uint64_t cnt0 = *B.counter;
   const int n = B.n_blocks;
@@ -1041,7 +1041,7 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
     const int Mi = uniform(P.in_M[i]);
     const uint64_t c0 = cnt0 + (uint64_t)j0;
     const int p = (int)(c0 & 1u);
-    const int qh = hh ? ring_slot(c0 + 16u, Mi) : ring_slot(c0, Mi);   // ring slot of block 8 hh
+    const int qh = hh ? ring_slot(c0 + 2u * NP, Mi) : ring_slot(c0, Mi);   // ring slot of block NP hh
     const uint32_t f0 = 2u * (uint32_t)(it.tile * TW + w * 16 * U + b16) + (uint32_t)comp;   // float in a row
     const uint32_t lane_bytes = 4u * f0;
     // delay line of input i, parity p: Mi rows from a uniform base
@@ -1074,18 +1074,18 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
     const uint32_t ch_bytes = hh ? (uint32_t)(8 * (P.ch_bank_off[ch[1]] - P.ch_bank_off[ch[0]])) : 0u;
     const uint32_t slot_bytes = (uint32_t)(hh ? McL[1] : McL[0]) * RB;
 
-    f4 acc[8][U];
+    f4 acc[NP][U];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < NP; ++q)
 #pragma unroll
       for (int u = 0; u < U; ++u) acc[q][u] = f4{0.f, 0.f, 0.f, 0.f};
 
     auto ldf = [](const char* base, uint32_t off) { return *reinterpret_cast<const float*>(base + off); };
-    // loader role of lanes 0..47: part 0, 1: delay-line row of block 8 part;
+    // loader role of lanes 0..47: part 0, 1: delay-line row of block NP part;
     // part 2 + 2 d + g: partition spectrum of channel g, slot set d (even, odd)
     const int part = lane < 48 ? (lane >> 3) : ((lane >> 3) - 6), within = lane & 7;
     const uint32_t tile_bytes = (uint32_t)(it.tile * TW + w * 16) * 8u;
-    const int gq = ring_slot(c0 + (part == 1 ? 16u : 0u), Mi);   // loader's ring slot of block 8 part
+    const int gq = ring_slot(c0 + (part == 1 ? 2u * NP : 0u), Mi);   // loader's ring slot of block NP part
     const int lg = part & 1;                                     // loader's channel (H parts)
     const uint32_t lch_bytes = lg ? (uint32_t)(8 * (P.ch_bank_off[ch[1]] - P.ch_bank_off[ch[0]])) : 0u;
     const uint32_t lslot_bytes = (uint32_t)(lg ? McL[1] : McL[0]) * RB;
@@ -1098,7 +1098,7 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
     // pairs those of so.
     auto run = [&](const int (&se)[2], const int (&so)[2]) {
       // Delay-line values by d = q - s (pair q at step s = mm - m0) in a
-      // circular buffer of R registers: d = 7 - s .. -s are in use at step s
+      // circular buffer of R registers: d = NP - 1 - s .. -s are in use at step s
       // and d = -s - 1 is read from the staging slot during step s.
       float W[R];
       float Bq[2][2];
@@ -1106,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
       const uint32_t he = ch_bytes + (uint32_t)(hh ? se[1] : se[0]) * slot_bytes + lane_bytes;
       const uint32_t ho = ch_bytes + (uint32_t)(hh ? so[1] : so[0]) * slot_bytes + lane_bytes;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < NP; ++q) {
         int r = (qh + q - m0) % Mi;
         r = r < 0 ? r + Mi : r;
         W[q] = ldf(xb, (uint32_t)r * RB + lane_bytes);
@@ -1149,7 +1149,7 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
         }
         // b. the products of step s
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < NP; ++q)
           acc[q][0] = __builtin_amdgcn_mfma_f32_4x4x1f32(W[(((q - S) % R) + R) % R], Bq[S & 1][q & 1], acc[q][0], 0,
                                                          0, 0);
         // c. stage row-step s + 2; d. fetch row-step s + 2 + PG
@@ -1180,7 +1180,15 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
       for (int g = 0; g < 2; ++g)
         if (b < nb) regular = regular && slot[g][b] == ((b & 1) ? so[g] : se[g]);
     if (!regular) {
-      if (threadIdx.x == 0) B.defer_list[atomicAdd(B.defer_count, 1)] = idx;
+      // the vector-ALU MAC takes time groups of 16 blocks: defer those of this
+      // group in its index space
+      if (threadIdx.x == 0) {
+        const int g16 = ((n + 1) / 2 + 15) / 16;
+        for (int h2 = 0; h2 < TB / 16; ++h2) {
+          const int gi16 = gi * (TB / 16) + h2;
+          if (cls + 32 * gi16 < n) B.defer_list[atomicAdd(B.defer_count, 1)] = 8 * ((pr >> 3) * g16 + gi16) + (pr & 7);
+        }
+      }
       continue;
     }
     run(se, so);
@@ -1191,7 +1199,7 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
     const int rowl = hh ? it.row[1] : it.row[0];
     const bool wr = hh < n_ch;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < NP; ++q)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const f4 c = acc[q][u];
@@ -1199,7 +1207,7 @@ __global__ __launch_bounds__(256) void k_tmfma(BatchArgs B) {
         const float p3 = __shfl_xor(c[3], 1);
 #pragma unroll
         for (int h2 = 0; h2 < 2; ++h2) {
-          const int t = q + 8 * h2;
+          const int t = q + NP * h2;
           const float cr = h2 ? c[2] : c[0];
           const float ci = h2 ? c[3] : c[1];
           const float pi = h2 ? p3 : p1;
@@ -1696,19 +1704,29 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
       if (shape.E == 1) {
         // matrix-core MAC: f32 spectra, up to two channels per item, time groups of 16
         if constexpr (DT == 0) {
-          if (shape.G > 2 || B.time_block != 16 || shape.V != 1 || shape.NW != 4) return hipErrorInvalidValue;
-          if (B.tile_width != 64 || B.tile_width > 2 * L || !B.defer_list || !B.defer_count)
+          if (shape.G > 2 || (B.time_block != 16 && B.time_block != 32) || shape.V != 1 ||
+              (shape.NW != 4 && shape.NW != 8))
             return hipErrorInvalidValue;
-          hipLaunchKernelGGL((k_tmfma<L, 12, DT>), dim3(grid), dim3(256), 0, s, B);
+          if (B.tile_width != 16 * shape.NW || B.tile_width > 2 * L || !B.defer_list || !B.defer_count)
+            return hipErrorInvalidValue;
+          const dim3 tb(64 * shape.NW);
+          if (B.time_block == 32) {
+            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma<L, 16, 20, 10, 8, DT>), dim3(grid), tb, 0, s, B);
+            else hipLaunchKernelGGL((k_tmfma<L, 16, 20, 10, 4, DT>), dim3(grid), tb, 0, s, B);
+          } else {
+            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma<L, 8, 12, 12, 8, DT>), dim3(grid), tb, 0, s, B);
+            else hipLaunchKernelGGL((k_tmfma<L, 8, 12, 12, 4, DT>), dim3(grid), tb, 0, s, B);
+          }
           e = hipGetLastError();
           if (e != hipSuccess) return e;
-          // the deferred units on the vector ALU: one wave per 64-bin tile
+          // the deferred units on the vector ALU: one wave per 64 bins of the tile
           BatchArgs Bd = B;
           Bd.from_list = 1;
+          const dim3 tv(B.tile_width);
           if (shape.G == 1)
-            hipLaunchKernelGGL((k_tmac<L, 1, 1, 16, DT>), dim3(grid), dim3(64), 0, s, Bd);
+            hipLaunchKernelGGL((k_tmac<L, 1, 1, 16, DT>), dim3(grid), tv, 0, s, Bd);
           else
-            hipLaunchKernelGGL((k_tmac<L, 1, 2, 16, DT>), dim3(grid), dim3(64), 0, s, Bd);
+            hipLaunchKernelGGL((k_tmac<L, 1, 2, 16, DT>), dim3(grid), tv, 0, s, Bd);
           e = hipGetLastError();
         } else {
           return hipErrorInvalidValue;

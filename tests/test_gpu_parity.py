@@ -473,7 +473,7 @@ def test_matrix_core_engine_matches_single_blocks_and_oracle(case, batch):
 
 
 # (chunk, vec, waves, group) of the matrix-core engine
-MFMA_SCHEDULES = [(0, 0, 0, 0), (2, 1, 1, 1), (3, 0, 2, 2), (1, 1, 4, 1), (200, 1, 1, 2), (5, 0, 4, 1)]
+MFMA_SCHEDULES = [(0, 0, 0, 0), (2, 1, 8, 1), (3, 0, 8, 2), (1, 1, 4, 1), (200, 1, 8, 2), (5, 0, 4, 1)]
 
 
 @pytest.mark.parametrize("sched", MFMA_SCHEDULES, ids=[f"c{s[0]}v{s[1]}w{s[2]}g{s[3]}" for s in MFMA_SCHEDULES])
@@ -492,12 +492,23 @@ def test_matrix_core_engine_schedules(case, sched):
 
 
 @pytest.mark.parametrize("batch", [64, 37, 23])
-def test_matrix_core_engine_large_batches(batch):
-    log(f"matrix-core large batch {batch}")
+@pytest.mark.parametrize("time_block", [16, 32])
+def test_matrix_core_engine_large_batches(batch, time_block):
+    """Time groups of 16 and 32 blocks; the stream switches slots at random
+    (most groups go to the vector-ALU MAC) or alternates them by parity (all
+    groups of inputs whose channels have equal partition counts stay on the
+    matrix cores)."""
+    log(f"matrix-core large batch {batch} time block {time_block}")
     wl = synth.random_small(seed=78, hop=128, n_channels=8, n_inputs=4, n_samples=128 * 150 + 9,
                             taps_range=(300, 9000), n_slots=3, p_switch=0.3)
     conv = make_convolver(wl, max_batch=64)
-    conv.configure_batch(engine=2)
+    conv.configure_batch(engine=2, time_block=time_block)
+    assert conv.info()["batch_time_block"] == time_block
+    got = gpu_streams(wl, conv=conv, batch=batch)
+    assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
+    # alternating slots, equal partition counts within an input: regular groups
+    wl.schedule[:] = (np.arange(wl.n_calls) % 2)[:, None].astype(np.int32)
+    conv.reset()
     got = gpu_streams(wl, conv=conv, batch=batch)
     conv.close()
     assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
