@@ -80,6 +80,7 @@ struct tvolap {
   void* d_fdl = nullptr;
   float* d_hist = nullptr;      // [2][I][L]
   float* d_ola = nullptr;       // [n_out][3L]
+  float2* d_ybus = nullptr;     // [n_out][2L] bus spectra of one block (mixdown)
   int32_t n_out = 0;            // output buses (C without a mixdown)
   bool mixdown = false;
   std::vector<int32_t> out_ptr, out_ch;   // bus e: channels out_ch[out_ptr[e] .. out_ptr[e+1])
@@ -163,7 +164,7 @@ struct tvolap {
     P.in_M = d_in_M; P.in_fdl_off = d_in_fdl_off; P.tw = d_tw; P.win = d_win;
     P.ch_row_base = d_ch_row_base; P.ch_nchunks = d_ch_nchunks; P.tile_width = tile_width;
     P.in_ch_ptr = d_in_ch_ptr; P.in_ch = d_in_ch;
-    P.n_out = n_out; P.out_ptr = d_out_ptr; P.out_ch = d_out_ch;
+    P.n_out = n_out; P.out_ptr = d_out_ptr; P.out_ch = d_out_ch; P.ybus = d_ybus;
     return P;
   }
 };
@@ -228,7 +229,7 @@ void free_all(tvolap_t* h) {
   h->graph = nullptr;
   free_work(h);
   free_batch_work(h);
-  dfree(h->d_bank); h->d_fdl = nullptr; dfree(h->d_hist); dfree(h->d_ola); dfree(h->d_sel);
+  dfree(h->d_bank); h->d_fdl = nullptr; dfree(h->d_ybus); dfree(h->d_hist); dfree(h->d_ola); dfree(h->d_sel);
   dfree(h->d_out_ptr); dfree(h->d_out_ch);
   dfree(h->d_counter); dfree(h->d_tw); dfree(h->d_win); dfree(h->d_ch_input); dfree(h->d_ch_M);
   dfree(h->d_ch_bank_off); dfree(h->d_in_M); dfree(h->d_in_fdl_off); dfree(h->d_taps);
@@ -607,6 +608,7 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   h->d_fdl = static_cast<char*>(h->d_bank) + h->bank_alloc_bytes;
   HIP_TRY(h, dalloc(&h->d_hist, (size_t)2 * h->I * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_ola, (size_t)h->n_out * 3 * L * sizeof(float)));
+  if (h->mixdown) HIP_TRY(h, dalloc(&h->d_ybus, (size_t)h->n_out * 2 * L * sizeof(float2)));
   HIP_TRY(h, dalloc(&h->d_out_ptr, (size_t)(h->n_out + 1) * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_out_ch, (size_t)h->C * sizeof(int32_t)));
   HIP_TRY(h, hipMemcpy(h->d_out_ptr, h->out_ptr.data(), (h->n_out + 1) * sizeof(int32_t), hipMemcpyHostToDevice));

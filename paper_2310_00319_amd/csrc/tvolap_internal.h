@@ -29,6 +29,7 @@ struct DevPlan {
   int32_t n_out;
   const int32_t* out_ptr;      // [n_out+1]
   const int32_t* out_ch;       // [C]
+  float2* ybus;                // [n_out][2L] bus spectra of one block (mixdown only, else NULL)
 };
 
 // One unit of per-block work. kind 1: the new spectrum of input `input`.

@@ -1465,6 +1465,46 @@ __global__ __launch_bounds__(64 * NW) void k_mac(DevPlan P, const WorkItem* __re
   write_partials<V, G, NW, false>(it, acc, red, ypart, tid & 63, tid >> 6, tid);
 }
 
+// Mixdown of one block: for 64 bins of bus e, the sum over the bus's channels
+// of each channel's spectrum Y (its partial rows plus the m = 0 term,
+// eq. 8) into P.ybus. Four slices of the channel list are summed apart and
+// added in a fixed order.
+template <int L, int DT>
+__global__ __launch_bounds__(256) void k_bus_sum1(DevPlan P, const float2* __restrict__ ypart,
+                                                  const typename Store<DT>::T* __restrict__ bank,
+                                                  const typename Store<DT>::T* __restrict__ fdl,
+                                                  const int32_t* __restrict__ sel,
+                                                  const uint64_t* __restrict__ counter) {
+  using ST = typename Store<DT>::T;
+  constexpr int N = 2 * L;
+  const int tid = threadIdx.x, kx = tid & 63, sl = tid >> 6;
+  const int k = blockIdx.x * 64 + kx, e = blockIdx.y;
+  const uint64_t cnt = *counter;
+  const int p = (int)(cnt & 1u);
+  const int TW = P.tile_width;
+  const int t = k / TW, b = k - t * TW;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int q = P.out_ptr[e] + sl; q < P.out_ptr[e + 1]; q += 4) {
+    const int c = P.out_ch[q];
+    const int i = P.ch_input[c];
+    const int Mi = P.in_M[i];
+    const ST* xrow = fdl + P.in_fdl_off[i] + ((int64_t)p * Mi + ring_slot(cnt, Mi)) * N;
+    int s = sel[c];
+    s = s < 0 ? 0 : (s >= P.K ? P.K - 1 : s);
+    const float2 X = unpack<DT>(xrow[k]);
+    const float2 H = unpack<DT>(bank[P.ch_bank_off[c] + (int64_t)s * P.ch_M[c] * N + k]);
+    float2 v = (k == 0) ? make_float2(H.x * X.x, H.y * X.y) : cmul(H, X);
+    const int nch = P.ch_nchunks[c];
+    const float2* src = ypart + ((int64_t)P.ch_row_base[c] + (int64_t)t * nch) * TW + b;
+    for (int j = 0; j < nch; ++j) v = cadd(v, src[(int64_t)j * TW]);
+    acc = cadd(acc, v);
+  }
+  __shared__ float2 red[4][64];
+  red[sl][kx] = acc;
+  __syncthreads();
+  if (sl == 0) P.ybus[(int64_t)e * N + k] = cadd(cadd(red[0][kx], red[1][kx]), cadd(red[2][kx], red[3][kx]));
+}
+
 // One workgroup per output bus: the sum of its channels' spectra, the inverse
 // transform and the overlap-add; the last workgroup to finish advances the
 // call count.
@@ -1491,9 +1531,12 @@ __global__ __launch_bounds__(64) void k_inv(DevPlan P, const float2* __restrict_
   float old[(4 * L + 63) / 64];
   ola_prefetch<L, 64>(st, old, tid);
   const int c0 = P.out_ptr[e], c1 = P.out_ptr[e + 1];
-  channel_spectrum<L, 64, DT, false>(P, ypart, bank, fdl, sel, P.out_ch[c0], p, cnt, Y, tid);
-  for (int q = c0 + 1; q < c1; ++q)
-    channel_spectrum<L, 64, DT, false, true>(P, ypart, bank, fdl, sel, P.out_ch[q], p, cnt, Y, tid);
+  if (P.ybus) {
+    // mixdown: the bus spectrum, summed over the bus's channels by k_bus_sum1
+    for (int k = tid; k < N; k += 64) Y[k] = P.ybus[(int64_t)e * N + k];
+  } else {
+    channel_spectrum<L, 64, DT, false>(P, ypart, bank, fdl, sel, P.out_ch[c0], p, cnt, Y, tid);
+  }
   __syncthreads();
   inverse_ola<L, 64>(Y, bufA, bufB, twl, old, st, out + (int64_t)e * out_stride, tid);
   if (tid == 0) {
@@ -1661,6 +1704,12 @@ hipError_t hop_inv(const DevPlan& P, int dtype, const float2* ypart, const void*
   return by_dtype(dtype, [&](auto Dc) {
     constexpr int DT = decltype(Dc)::value;
     using ST = typename Store<DT>::T;
+    if (P.ybus) {
+      hipLaunchKernelGGL((k_bus_sum1<L, DT>), dim3(2 * L / 64, P.n_out), dim3(256), 0, s, P, ypart,
+                         static_cast<const ST*>(bank), static_cast<const ST*>(fdl), sel, counter);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_inv<L, DT>), dim3(P.n_out), dim3(64), 0, s, P, ypart, static_cast<const ST*>(bank),
                        static_cast<const ST*>(fdl), sel, ola, out, out_stride, copy_sel, sel_store, done, counter);
     return hipGetLastError();
@@ -1719,14 +1768,16 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
           }
           e = hipGetLastError();
           if (e != hipSuccess) return e;
-          // the deferred units on the vector ALU: one wave per 64 bins of the tile
+          // the deferred units on the vector ALU: one wave per 64 bins of the
+          // tile, a grid of at most 1024 workgroups striding over the list
           BatchArgs Bd = B;
           Bd.from_list = 1;
           const dim3 tv(B.tile_width);
+          const dim3 gd(grid < 1024 ? grid : 1024);
           if (shape.G == 1)
-            hipLaunchKernelGGL((k_tmac<L, 1, 1, 16, DT>), dim3(grid), tv, 0, s, Bd);
+            hipLaunchKernelGGL((k_tmac<L, 1, 1, 16, DT>), gd, tv, 0, s, Bd);
           else
-            hipLaunchKernelGGL((k_tmac<L, 1, 2, 16, DT>), dim3(grid), tv, 0, s, Bd);
+            hipLaunchKernelGGL((k_tmac<L, 1, 2, 16, DT>), gd, tv, 0, s, Bd);
           e = hipGetLastError();
         } else {
           return hipErrorInvalidValue;
