@@ -40,8 +40,9 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # 16-bit spectra are multiplied with two-element dot products (4 flop per lane
 # per instruction) accumulating in FP32: twice the FMA rate.
 DOT2_PEAK_TFLOPS = 2 * VALU_PEAK_TFLOPS
-# Dense FP32 matrix-core (MFMA) peak of the chip.
+# Dense matrix-core (MFMA) peaks of the chip: FP32, and bf16/f16 inputs.
 MFMA_F32_PEAK_TFLOPS = 157.3
+MFMA_16_PEAK_TFLOPS = 2500.0
 
 WORKLOADS = {
     "binaural": dict(desc="64 sources x 2 ears = 128 channels, L=256 (blocks 512, FFT 1024), 96000-tap IRs "
@@ -481,9 +482,11 @@ def run(args, spec, wl, stream):
         tfs = kflops / (mac_ms * 1e-3) / 1e12
         floor_hbm = kbytes / (HBM_PEAK_GBS * 1e9)
         mfma = info["batch_engine"] == 2
-        kname = "k_tmfma" if mfma else "k_tmac"
-        alu_peak = (MFMA_F32_PEAK_TFLOPS if mfma else VALU_PEAK_TFLOPS) if spec["dtype"] == "f32" \
-            else DOT2_PEAK_TFLOPS
+        kname = ("k_tmfma" if spec["dtype"] == "f32" else "k_tmfma16") if mfma else "k_tmac"
+        if mfma:
+            alu_peak = MFMA_F32_PEAK_TFLOPS if spec["dtype"] == "f32" else MFMA_16_PEAK_TFLOPS
+        else:
+            alu_peak = VALU_PEAK_TFLOPS if spec["dtype"] == "f32" else DOT2_PEAK_TFLOPS
         floor_alu = kflops / (alu_peak * 1e12)
         per_block = info["mac_bytes_per_block"] * wl.n_calls / calls_per_step
         tr = measured_traffic(f"{args.workload} batch{args.batch} {kname}")
@@ -492,18 +495,18 @@ def run(args, spec, wl, stream):
         alu = {"achieved": round(tfs, 2), "peak": round(alu_peak, 2), "unit": "TFLOP/s",
                "frac": round(tfs / alu_peak, 4), "flops_per_launch": int(kflops),
                "floor_us": round(floor_alu * 1e6, 2),
-               "peak_note": ("dense FP32 matrix-core peak (4x4x1 MFMAs, 16 bins each)" if mfma else
+               "peak_note": ("dense matrix-core peak of the input type (16-bin 4x4 MFMAs)" if mfma else
                              "FP32 FMA issue rate without packed-FP32 instructions (256 CU x 4 SIMD x 16 lanes x "
-                             "2 flop x 2.4 GHz); the published packed figure is 157.3") if spec["dtype"] == "f32"
-               else ("two-element 16-bit dot products with FP32 accumulation: 256 CU x 4 SIMD x 16 lanes x "
-                     "4 flop x 2.4 GHz")}
+                             "2 flop x 2.4 GHz); the published packed figure is 157.3" if spec["dtype"] == "f32"
+                             else "two-element 16-bit dot products with FP32 accumulation: 256 CU x 4 SIMD x 16 "
+                                  "lanes x 4 flop x 2.4 GHz")}
         cname = "mfma" if mfma else "alu"
         main, other = (("hbm", hbm), (cname, alu)) if floor_hbm >= floor_alu else ((cname, alu), ("hbm", hbm))
         roof = {"bound": main[0], "achieved": main[1]["achieved"], "peak": main[1]["peak"], "unit": main[1]["unit"],
                 "frac": main[1]["frac"], "traffic": tr[0] if tr else None,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "traffic_source": tr[1] if tr else None,
-                "kernel": (("k_tmfma (time-blocked spectral MAC of eq. 8 on matrix cores)" if mfma else
+                "kernel": ((kname + " (time-blocked spectral MAC of eq. 8 on matrix cores)" if mfma else
                             "k_tmac (time-blocked spectral MAC of eq. 8 over a batch of blocks)")),
                 "avg_launch_us": round(mac_ms * 1e3, 3), main[0]: main[1], other[0]: other[1],
                 "bytes_note": "unique delay-line and partition spectra of each call",

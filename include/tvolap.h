@@ -233,14 +233,14 @@ int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us);
  * matrix-core engine; 0 = 16 when max_batch >= 32, else 8); group: channels
  * of one input per work item, 1 or 2 (two channels share the delay-line loads; 0 = 2 when an input
  * feeds several channels); engine: 1 = vector ALU (multiply-adds or packed
- * dot products per complex product), 2 = matrix cores (f32 spectra only: per
- * bin, the products of a time group of 16 blocks and the two channels of an
- * input are 4x4 outer products, one 16-bin MFMA each; 16 bins per wave, so vec
- * must be 0 or 1; time groups of 16 or 32 blocks, 0 = 32 when max_batch >= 64;
- * time groups whose slots do not alternate by parity go to the vector ALU),
- * 0 = 1. Waits for the stream; rebuilds the
- * batched work list. Errors: EINVAL (also engine 2 with 16-bit spectra),
- * ESTATE during capture, ENOMEM/EDEVICE. */
+ * dot products per complex product), 2 = matrix cores (per bin, the products
+ * of a time group and the two channels of an input form one 16-bin MFMA per
+ * step: 4x4x1 outer products for f32 spectra, 4x4x4 products over two
+ * partitions for bf16/f16; 16 bins per wave, so vec must be 0 or 1; time
+ * groups of 16 or 32 blocks, 0 = 32 when max_batch >= 64; time groups whose
+ * slots do not alternate by parity go to the vector ALU), 0 = 1. Waits for
+ * the stream; rebuilds the batched work list. Errors: EINVAL, ESTATE during
+ * capture, ENOMEM/EDEVICE. */
 int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t waves, int32_t time_block,
                            int32_t group, int32_t engine);
 

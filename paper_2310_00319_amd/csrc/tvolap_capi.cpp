@@ -375,7 +375,7 @@ void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
   // time groups of 16 blocks (one bin per lane) when calls can hold 32 blocks
   int V = (bc.vec == 1) ? 1 : 2;
   int TB = bc.time_block == 16 ? 16 : (bc.time_block == 8 ? 8 : (h->max_batch >= 32 ? 16 : 8));
-  const int engine = (bc.engine == 2 && h->dtype == 0) ? 2 : 1;
+  const int engine = bc.engine == 2 ? 2 : 1;
   h->bshape.E = (engine == 2 && mfma_offsets_fit(h)) ? 1 : 0;   // else 32-bit byte offsets do not reach
   // bins per lane (vector ALU), or per lane group as 16-bin sub-tiles (matrix cores)
   const int bins = h->bshape.E == 1 ? 16 : 64;
@@ -1035,7 +1035,6 @@ int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t wave
   if (time_block == 16 && vec == 2) return fail(h, TVOLAP_EINVAL, "time_block 16 needs vec 1");
   if (group != 0 && group != 1 && group != 2) return fail(h, TVOLAP_EINVAL, "group must be 0, 1 or 2");
   if (engine < 0 || engine > 2) return fail(h, TVOLAP_EINVAL, "engine must be 0, 1 or 2");
-  if (engine == 2 && h->dtype != 0) return fail(h, TVOLAP_EINVAL, "the matrix-core engine needs f32 spectra");
   if (engine == 2 && (vec == 2 || time_block == 8))
     return fail(h, TVOLAP_EINVAL, "the matrix-core engine runs vec 1 and time groups of 16");
   BatchChoice c;
@@ -1104,8 +1103,7 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
   }
   std::vector<int> groups = {fan >= 2 ? 2 : 1};
   if (fan >= 2) groups.push_back(1);
-  std::vector<int> engines = {1};
-  if (h->dtype == 0) engines.push_back(2);
+  const std::vector<int> engines = {1, 2};
   for (int eng : engines)
   for (int grp : groups)
   for (int tb : tbs)

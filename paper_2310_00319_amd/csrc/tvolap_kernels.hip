@@ -1223,6 +1223,256 @@ __global__ __launch_bounds__(64 * NWV) void k_tmfma(BatchArgs B) {
   }
 }
 
+// Matrix-core form of the time-blocked MAC for 16-bit (bf16 / f16) spectra.
+// One 4x4x4 MFMA with 16 blocks takes 16 bins; in each, K runs over two
+// partitions m, m + 1 and (Re, Im): A rows are (X(t, m), X(t, m + 1)) of four
+// blocks t = q + NPQ i (raw delay-line words), B columns are the two channels'
+// (H(m), H(m + 1)) arranged so that the sums are Re Y and Im Y directly:
+// (Re H, -Im H) for the Re column, (Im H, Re H) for the Im column (products of
+// 16-bit values are exact in FP32; the sums are FP32). The packed DC / Nyquist
+// bin takes (Re H, 0) and (0, Im H). Quad q at partition pair m + 2 needs the
+// delay-line pairs quad q - 2 used at m, so each lane keeps a circular buffer of
+// word pairs and reads two new pairs per step. Staging as in k_tmfma: per step
+// 64 lanes fetch 16 bytes each (four delay-line rows x two values, and two
+// partitions x two slot sets x two channels of partition spectra, 64 B each),
+// write them to the wave's LDS slot and read their operands back. Regular time
+// groups only; others are deferred to k_tmac as in k_tmfma.
+template <int L, int NPQ, int R, int PG, int NWV, int DT>
+__global__ __launch_bounds__(64 * NWV) void k_tmfma16(BatchArgs B) {
+  static_assert(DT == 1 || DT == 2, "16-bit spectra");
+  static_assert(NPQ == 4 || NPQ == 8, "quads per time group");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  typedef short s4 __attribute__((ext_vector_type(4)));
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  constexpr int TB = 4 * NPQ;               // blocks of one parity per time group
+  constexpr int N = 2 * L;
+  constexpr uint32_t RB = 4u * N;           // bytes per row (16-bit complex words)
+  constexpr int LS = 4;                     // staging slots per wave
+  constexpr int PER = std::lcm(std::lcm(R, LS), std::lcm(PG, 2));
+  static_assert(R >= NPQ + 2 && PG >= 3, "window and load ring");
+  __shared__ u4 stage[NWV][LS][64];
+  const int TW = B.tile_width;              // 16 bins per wave
+  const DevPlan& P = B.P;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int b16 = lane >> 2;                // bin of the lane's MFMA block
+  const int rowi = lane & 3;                // A: row (block q + NPQ rowi)
+  const int gl = (lane >> 1) & 1;           // B and C: channel
+  const int comp = lane & 1;                // B and C: Re (0) or Im (1)
+  const uint64_t cnt0 = *B.counter;
+  const int n = B.n_blocks;
+  const int groups = ((n + 1) / 2 + TB - 1) / TB;
+  const int pairs = 2 * B.n_mac;
+  const int lanes8 = (pairs + 7) / 8;
+  const int total = 8 * lanes8 * groups;
+  const char* bank = static_cast<const char*>(B.bank);
+  const char* fdl = static_cast<const char*>(B.fdl);
+  for (int idx = blockIdx.x; idx < total; idx += gridDim.x) {
+    const int x = idx & 7, y = idx >> 3;
+    const int gi = y % groups;
+    const int pr = x + 8 * (y / groups);
+    if (pr >= pairs) continue;
+    const int cls = pr & 1;
+    const WorkItem it = B.items[pr >> 1];
+    const int j0 = cls + 2 * TB * gi;
+    if (j0 >= n) continue;
+    const int nb = min(TB, (n - j0 + 1) / 2);
+    const int i = uniform(it.input);
+    const int n_ch = uniform(it.n_ch);
+    const int m0 = uniform(it.m0), m1 = uniform(it.m1);
+    const int Mi = uniform(P.in_M[i]);
+    const uint64_t c0 = cnt0 + (uint64_t)j0;
+    const int p = (int)(c0 & 1u);
+    const int bin = it.tile * TW + w * 16 + b16;
+    const char* xb = fdl + 4 * (P.in_fdl_off[i] + (int64_t)p * Mi * N);
+    const uint32_t ring_bytes = (uint32_t)Mi * RB;
+    int ch[2], McL[2], Mc[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      ch[g] = uniform(g < n_ch ? it.ch[g] : it.ch[0]);
+      McL[g] = uniform(P.ch_M[ch[g]]);
+      Mc[g] = g < n_ch ? McL[g] : 0;
+    }
+    int slot[2][TB];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) slot[g][b] = B.sel[(int64_t)(j0 + 2 * min(b, nb - 1)) * B.sel_stride + ch[g]];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int sv = uniform(slot[g][b]);
+        slot[g][b] = sv < 0 ? 0 : (sv >= P.K ? P.K - 1 : sv);
+      }
+    int se[2], so[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      se[g] = slot[g][0];
+      so[g] = slot[g][nb > 1 ? 1 : 0];
+    }
+    bool regular = m1 <= Mc[0] && (n_ch < 2 || m1 <= Mc[1]);
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+        if (b < nb) regular = regular && slot[g][b] == ((b & 1) ? so[g] : se[g]);
+    if (!regular) {
+      if (threadIdx.x == 0) {
+        const int g16 = ((n + 1) / 2 + 15) / 16;
+        for (int h2 = 0; h2 < TB / 16; ++h2) {
+          const int gi16 = gi * (TB / 16) + h2;
+          if (cls + 32 * gi16 < n) B.defer_list[atomicAdd(B.defer_count, 1)] = 8 * ((pr >> 3) * g16 + gi16) + (pr & 7);
+        }
+      }
+      continue;
+    }
+    const char* hb = bank + 4 * P.ch_bank_off[ch[0]];
+    const uint32_t ch1_bytes = (uint32_t)(4 * (P.ch_bank_off[ch[1]] - P.ch_bank_off[ch[0]]));
+    const uint32_t xbo = (uint32_t)(xb - bank);
+
+    // B operand arrangement of the lane: (Re H, -Im H) for the Re column,
+    // (Im H, Re H) for the Im column; the DC lane keeps one half
+    const bool dcl = bin == 0;
+    const uint32_t bsh = (comp && !dcl) ? 16u : 0u;
+    const uint32_t bxm = (comp || dcl) ? 0u : 0x80000000u;
+    const uint32_t bam = dcl ? (comp ? 0xffff0000u : 0x0000ffffu) : 0xffffffffu;
+    auto barr = [&](uint32_t v) { return (__builtin_amdgcn_alignbit(v, v, bsh) ^ bxm) & bam; };
+
+    // loader role: pieces 0..7: delay-line row of block NPQ (piece >> 1), value
+    // d = -2k - (piece & 1); pieces 8..15: partition m0 + 2k + dl, slot set sd,
+    // channel lg (64 B each, four lanes of 16 B)
+    const int piece = lane >> 2, within = lane & 3;
+    const bool xl = piece < 8;
+    const int li = piece >> 1, lv = piece & 1;
+    const int hp = piece - 8, ldl = (hp >> 2) & 1, lsd = (hp >> 1) & 1, lg = hp & 1;
+    const uint32_t pos_bytes = (uint32_t)(it.tile * TW + w * 16) * 4u + 16u * (uint32_t)within;
+    const int gq = ring_slot(c0 + 2u * (uint32_t)(NPQ * li), Mi);
+    const uint32_t* stw = reinterpret_cast<const uint32_t*>(stage[w][0]);
+    u4* st = stage[w][0];
+
+    f4 acc[NPQ];
+#pragma unroll
+    for (int q = 0; q < NPQ; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    {
+      // window of pairs (X_i[c], X_i[c - 1]) by c = q - 2s, X_i[e] = X(block
+      // NPQ rowi + e, partition m0): c = NPQ - 1 - 2s .. -2s in use at step s,
+      // -2s - 1 and -2s - 2 read during step s
+      uint2 W[R];
+      uint32_t Bq[2][2][2];                 // [step parity][set][partition of the pair]
+      u4 G[PG];
+      const int qr = ring_slot(c0 + 2u * (uint32_t)(NPQ * rowi), Mi);
+      auto xword = [&](int e) {
+        int r = (qr + e - m0) % Mi;
+        r = r < 0 ? r + Mi : r;
+        return *reinterpret_cast<const uint32_t*>(xb + (uint32_t)r * RB + 4u * (uint32_t)bin);
+      };
+#pragma unroll
+      for (int c = 0; c < NPQ; ++c) W[c] = make_uint2(xword(c), xword(c - 1));
+      {
+        const uint32_t hbase = (gl ? ch1_bytes : 0u) + 4u * (uint32_t)bin + (uint32_t)m0 * RB;
+        const uint32_t sbe = (uint32_t)(gl ? McL[1] * se[1] : McL[0] * se[0]) * RB;
+        const uint32_t sbo = (uint32_t)(gl ? McL[1] * so[1] : McL[0] * so[0]) * RB;
+        const bool on1 = m0 + 1 < m1;
+        Bq[0][0][0] = barr(*reinterpret_cast<const uint32_t*>(hb + hbase + sbe));
+        Bq[0][0][1] = on1 ? barr(*reinterpret_cast<const uint32_t*>(hb + hbase + sbe + RB)) : 0u;
+        Bq[0][1][0] = barr(*reinterpret_cast<const uint32_t*>(hb + hbase + sbo));
+        Bq[0][1][1] = on1 ? barr(*reinterpret_cast<const uint32_t*>(hb + hbase + sbo + RB)) : 0u;
+      }
+      // loader offsets from the bank base, row-step 1 (k = 1)
+      const bool xlr = xl;
+      const uint32_t lo = xlr ? xbo + pos_bytes : 0u;
+      const uint32_t wrap = xlr ? ring_bytes : 0u;
+      uint32_t goff;
+      {
+        int r = (gq - m0 - 2 - lv) % Mi;
+        r = r < 0 ? r + Mi : r;
+        const int lslot = lsd ? (lg ? so[1] : so[0]) : (lg ? se[1] : se[0]);
+        const uint32_t lh = (lg ? ch1_bytes : 0u) + (uint32_t)(lg ? McL[1] : McL[0]) * (uint32_t)lslot * RB + pos_bytes;
+        goff = xlr ? lo + (uint32_t)r * RB : (uint32_t)(hb - bank) + lh + (uint32_t)(m0 + 2 + ldl) * RB;
+      }
+      auto gload = [&](u4& o) {
+        o = *reinterpret_cast<const u4*>(bank + goff);
+        // two rows per step: down the ring (wrapping) or up the bank
+        uint32_t dn = goff - 2 * RB;
+        dn = dn < lo ? dn + wrap : dn;
+        dn = dn < lo ? dn + wrap : dn;             // rings of one row
+        goff = xlr ? dn : goff + 2 * RB;
+      };
+#pragma unroll
+      for (int k = 1; k <= PG; ++k) gload(G[k % PG]);
+      st[1 * 64 + lane] = G[1];
+      gload(G[1]);
+      // piece word index of the lane's operands in a slot
+      const int ax0 = 16 * (2 * rowi) + b16;          // X_i[-2k] (value 0), X_i[-2k - 1] at +16
+      // row-step 0's second value, X_i[-1], which step 0 reads from slot 0
+      if ((lane & 3) == rowi) reinterpret_cast<uint32_t*>(stage[w][0])[ax0 + 16] = W[0].y;
+      const int bh = 16 * (8 + gl) + b16;             // H: + 32 * set + 64 * partition
+      auto advance = [&](int mm, auto sc, auto tailc) {
+        constexpr int S = decltype(sc)::value;       // step index mod PER
+        constexpr bool TAIL = decltype(tailc)::value;
+        // a. operands of row-step s + 1: pairs c = -2s - 1 and -2s - 2, spectra
+        //    of partitions m + 2, m + 3
+        {
+          const uint32_t* sp = stw + ((S + 1) % LS) * 256;   // row-step s + 1
+          const uint32_t* sq = stw + (S % LS) * 256;         // row-step s
+          const uint32_t x0 = sp[ax0], x1 = sp[ax0 + 16];      // X_i[-2s - 2], X_i[-2s - 3]
+          const uint32_t xp = sq[ax0 + 16];                    // X_i[-2s - 1]
+          W[(((-2 * S - 1) % R) + R) % R] = make_uint2(xp, x0);
+          W[(((-2 * S - 2) % R) + R) % R] = make_uint2(x0, x1);
+          // partitions past m1: only in the tail, and the second one also in
+          // the last step of a full period (an odd partition count)
+          const bool on2 = !TAIL || mm + 2 < m1;
+          const bool on3 = (!TAIL && S != PER - 1) || mm + 3 < m1;
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            const uint32_t h2 = sp[bh + 32 * d], h3 = sp[bh + 32 * d + 64];
+            Bq[(S + 1) & 1][d][0] = on2 ? barr(h2) : 0u;
+            Bq[(S + 1) & 1][d][1] = on3 ? barr(h3) : 0u;
+          }
+        }
+        // b. the products of step s
+#pragma unroll
+        for (int q = 0; q < NPQ; ++q) {
+          const uint2 a = W[(((q - 2 * S) % R) + R) % R];
+          const uint2 b2 = make_uint2(Bq[S & 1][q & 1][0], Bq[S & 1][q & 1][1]);
+          if constexpr (DT == 1)
+            acc[q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b2),
+                                                            acc[q], 0, 0, 0);
+          else
+            acc[q] = __builtin_amdgcn_mfma_f32_4x4x4f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b2),
+                                                        acc[q], 0, 0, 0);
+        }
+        // c. stage row-step s + 2; d. fetch row-step s + 2 + PG
+        st[((S + 2) % LS) * 64 + lane] = G[(S + 2) % PG];
+        gload(G[(S + 2) % PG]);
+      };
+      int mb = m0;
+      for (; mb + 2 * PER <= m1; mb += 2 * PER)
+        static_for<PER>([&](auto sc) { advance(mb + 2 * decltype(sc)::value, sc, std::false_type{}); });
+      static_for<PER>([&](auto sc) {
+        if (mb + 2 * decltype(sc)::value < m1) advance(mb + 2 * decltype(sc)::value, sc, std::true_type{});
+      });
+    }
+    // C: lane column (channel gl, component comp), register r = block q + NPQ r
+    const int rowl = gl ? it.row[1] : it.row[0];
+    if (gl < n_ch) {
+#pragma unroll
+      for (int q = 0; q < NPQ; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int t = q + NPQ * r;
+          if (t < nb) {
+            float* dst = reinterpret_cast<float*>(B.ypart + ((int64_t)(j0 + 2 * t) * B.n_rows + rowl) * TW) +
+                         2 * (w * 16 + b16) + comp;
+            *dst = acc[q][r];
+          }
+        }
+    }
+  }
+}
+
 // Mixdown of a batch: for block j, bus e and 64 bins, the sum over the bus's
 // channels and their partition chunks of the partial rows (the channels'
 // spectra Y, eq. 8, are added before one inverse transform per bus), written
@@ -1751,8 +2001,33 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if (B.n_mac > 0) {
       if (shape.E == 1) {
-        // matrix-core MAC: f32 spectra, up to two channels per item, time groups of 16
-        if constexpr (DT == 0) {
+        // matrix-core MAC: up to two channels per item, time groups of 16 or 32
+        if constexpr (DT != 0) {
+          if (shape.G > 2 || (B.time_block != 16 && B.time_block != 32) || shape.V != 1 ||
+              (shape.NW != 4 && shape.NW != 8))
+            return hipErrorInvalidValue;
+          if (B.tile_width != 16 * shape.NW || B.tile_width > 2 * L || !B.defer_list || !B.defer_count)
+            return hipErrorInvalidValue;
+          const dim3 tb(64 * shape.NW);
+          if (B.time_block == 32) {
+            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma16<L, 8, 10, 10, 8, DT>), dim3(grid), tb, 0, s, B);
+            else hipLaunchKernelGGL((k_tmfma16<L, 8, 10, 10, 4, DT>), dim3(grid), tb, 0, s, B);
+          } else {
+            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma16<L, 4, 6, 12, 8, DT>), dim3(grid), tb, 0, s, B);
+            else hipLaunchKernelGGL((k_tmfma16<L, 4, 6, 12, 4, DT>), dim3(grid), tb, 0, s, B);
+          }
+          e = hipGetLastError();
+          if (e != hipSuccess) return e;
+          BatchArgs Bd = B;
+          Bd.from_list = 1;
+          const dim3 tv(B.tile_width);
+          const dim3 gd(grid < 1024 ? grid : 1024);
+          if (shape.G == 1)
+            hipLaunchKernelGGL((k_tmac<L, 1, 1, 16, DT>), gd, tv, 0, s, Bd);
+          else
+            hipLaunchKernelGGL((k_tmac<L, 1, 2, 16, DT>), gd, tv, 0, s, Bd);
+          e = hipGetLastError();
+        } else {
           if (shape.G > 2 || (B.time_block != 16 && B.time_block != 32) || shape.V != 1 ||
               (shape.NW != 4 && shape.NW != 8))
             return hipErrorInvalidValue;
@@ -1779,8 +2054,6 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
           else
             hipLaunchKernelGGL((k_tmac<L, 1, 2, 16, DT>), gd, tv, 0, s, Bd);
           e = hipGetLastError();
-        } else {
-          return hipErrorInvalidValue;
         }
       } else {
       e = by_bshape(shape, [&](auto Vc, auto Gc) {

@@ -514,13 +514,56 @@ def test_matrix_core_engine_large_batches(batch, time_block):
     assert rel_rms_per_channel(got, oracle_streams(wl)).max() <= TOL_F32
 
 
-def test_matrix_core_engine_rejected_for_16_bit_spectra():
-    wl = synth.random_small(seed=79, hop=64, n_channels=2, n_inputs=1, n_samples=64 * 10,
-                            taps_range=(10, 300), n_slots=1, p_switch=0.0)
-    conv = make_convolver(wl, "bf16")
-    with pytest.raises(Exception, match="matrix-core"):
-        conv.configure_batch(engine=2)
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("case", [SMALL_CASES[0], SMALL_CASES[1], SMALL_CASES[3], SMALL_CASES[4], SMALL_CASES[6]],
+                         ids=["s1_L64", "s2_L128", "s4_L512", "s5_L64", "s7_L256"])
+@pytest.mark.parametrize("batch", [5, 16])
+def test_matrix_core_engine_16_bit_spectra(case, batch, dtype):
+    """bf16/f16 spectra on matrix cores (4x4x4 MFMAs over two partitions): the
+    same bar as the vector-ALU path against the oracle with spectra rounded the
+    same way, and close to the vector-ALU result (exact 16-bit products, FP32
+    sums in another order)."""
+    seed, L, C, I, N, tr, K, p = case
+    log(f"matrix-core {dtype} case {case} batch {batch}")
+    wl = synth.random_small(seed=seed + 300, hop=L, n_channels=C, n_inputs=I, n_samples=N,
+                            taps_range=tr, n_slots=K, p_switch=p)
+    vec = gpu_streams(wl, dtype, batch=batch)
+    conv = make_convolver(wl, dtype)
+    conv.configure_batch(engine=2)
+    assert conv.info()["batch_engine"] == 2
+    got = gpu_streams(wl, dtype, conv=conv, batch=batch)
     conv.close()
+    assert rel_rms_per_channel(got, vec).max() <= 1e-5
+    assert rel_rms_per_channel(got, oracle_streams(wl, dtype=dtype)).max() <= 2e-4
+
+
+@pytest.mark.parametrize("time_block", [16, 32])
+@pytest.mark.parametrize("batch", [64, 37])
+def test_matrix_core_engine_16_bit_regular_groups(batch, time_block):
+    """Slots alternating by parity and equal partition counts per input: every
+    time group stays on the matrix cores (none deferred)."""
+    log(f"matrix-core bf16 regular, batch {batch} time block {time_block}")
+    wl = synth.random_small(seed=81, hop=128, n_channels=8, n_inputs=4, n_samples=128 * 150 + 9,
+                            taps_range=(5000, 5000), n_slots=3, p_switch=0.0)
+    wl.schedule[:] = (np.arange(wl.n_calls) % 2)[:, None].astype(np.int32)
+    vec = gpu_streams(wl, "bf16", batch=16)
+    conv = make_convolver(wl, "bf16", max_batch=64)
+    conv.configure_batch(engine=2, time_block=time_block)
+    got = gpu_streams(wl, "bf16", conv=conv, batch=batch)
+    conv.close()
+    assert rel_rms_per_channel(got, vec).max() <= 1e-5
+    assert rel_rms_per_channel(got, oracle_streams(wl, dtype="bf16")).max() <= 2e-4
+
+
+def test_full_binaural_bf16_bench_configuration_matrix_cores():
+    log("full binaural bf16, 64-block calls from a graph, matrix-core engine")
+    wl = synth.binaural()
+    chans = [0, 63, 127]
+    got = gpu_streams_graph(wl, "bf16", batch=64, channels=chans, schedule=dict(engine=2))
+    err_q = rel_rms_per_channel(got, oracle_streams(wl, chans, dtype="bf16"))
+    snr = -20 * np.log10(rel_rms_per_channel(got, oracle_streams(wl, chans)))
+    log(f"binaural bf16 (matrix cores): rel-RMS vs rounded oracle {err_q.max():.3e}, SNR min {snr.min():.1f} dB")
+    assert err_q.max() <= 2e-4 and snr.min() >= 40.0
 
 
 def test_full_binaural_bench_configuration_matrix_cores():
