@@ -1000,8 +1000,8 @@ __global__ __launch_bounds__(64 * NWV) void k_tmfma(BatchArgs B) {
   constexpr int N = 2 * L;
   constexpr uint32_t RB = 8u * N;           // bytes per delay-line / partition row
   constexpr int LS = 4;                     // staging slots per wave
-  constexpr int PER = std::lcm(std::lcm(R, LS), PG);   // unroll period (static register indices)
-  static_assert(R >= NP + 1 && PG >= 3, "window and load ring");
+  constexpr int PER = std::lcm(std::lcm(R, LS), std::lcm(PG, 3));   // unroll period (static register indices)
+  static_assert(R >= NP + 2 && PG >= 4, "window and load ring");
   // Staging: per step a wave needs two delay-line row pieces and four
   // partition-spectrum row pieces of 128 B (its 16 bins); 48 lanes fetch them
   // with one 16-byte load each (lanes 48..63 repeat delay-line pieces), the
@@ -1098,10 +1098,11 @@ __global__ __launch_bounds__(64 * NWV) void k_tmfma(BatchArgs B) {
     // pairs those of so.
     auto run = [&](const int (&se)[2], const int (&so)[2]) {
       // Delay-line values by d = q - s (pair q at step s = mm - m0) in a
-      // circular buffer of R registers: d = NP - 1 - s .. -s are in use at step s
-      // and d = -s - 1 is read from the staging slot during step s.
+      // circular buffer of R registers: d = NP - 1 - s .. -s are in use at
+      // step s, d = -s - 1 was read during step s - 1 and d = -s - 2 is read
+      // from its staging slot during step s (two steps ahead of its use).
       float W[R];
-      float Bq[2][2];
+      float Bq[3][2];
       f4 G[PG];                                // row-step k (d = -k, partition m0 + k) in G[k mod PG]
       const uint32_t he = ch_bytes + (uint32_t)(hh ? se[1] : se[0]) * slot_bytes + lane_bytes;
       const uint32_t ho = ch_bytes + (uint32_t)(hh ? so[1] : so[0]) * slot_bytes + lane_bytes;
@@ -1137,24 +1138,32 @@ __global__ __launch_bounds__(64 * NWV) void k_tmfma(BatchArgs B) {
 #pragma unroll
       for (int k = 1; k <= PG; ++k) gload(G[k % PG]);
       st[1 * 64 + lane] = G[1];
+      st[2 * 64 + lane] = G[2];
       gload(G[1]);                             // row-step 1 + PG
+      gload(G[2]);                             // row-step 2 + PG
+      {
+        const float* sl = stf + 1 * 256;       // row-step 1
+        W[R - 1] = sl[rx];
+        Bq[1][0] = sl[64 + rx];
+        Bq[1][1] = sl[128 + rx];
+      }
       auto advance = [&](auto sc) {
         constexpr int S = decltype(sc)::value;   // step index mod PER
-        // a. operands of row-step s + 1 from its staging slot
+        // a. operands of row-step s + 2 from its staging slot
         {
-          const float* sl = stf + ((S + 1) % LS) * 256;
-          W[(((-S - 1) % R) + R) % R] = sl[rx];
-          Bq[(S + 1) & 1][0] = sl[64 + rx];
-          Bq[(S + 1) & 1][1] = sl[128 + rx];
+          const float* sl = stf + ((S + 2) % LS) * 256;
+          W[(((-S - 2) % R) + R) % R] = sl[rx];
+          Bq[(S + 2) % 3][0] = sl[64 + rx];
+          Bq[(S + 2) % 3][1] = sl[128 + rx];
         }
         // b. the products of step s
 #pragma unroll
         for (int q = 0; q < NP; ++q)
-          acc[q][0] = __builtin_amdgcn_mfma_f32_4x4x1f32(W[(((q - S) % R) + R) % R], Bq[S & 1][q & 1], acc[q][0], 0,
+          acc[q][0] = __builtin_amdgcn_mfma_f32_4x4x1f32(W[(((q - S) % R) + R) % R], Bq[S % 3][q & 1], acc[q][0], 0,
                                                          0, 0);
-        // c. stage row-step s + 2; d. fetch row-step s + 2 + PG
-        st[((S + 2) % LS) * 64 + lane] = G[(S + 2) % PG];
-        gload(G[(S + 2) % PG]);
+        // c. stage row-step s + 3; d. fetch row-step s + 3 + PG
+        st[((S + 3) % LS) * 64 + lane] = G[(S + 3) % PG];
+        gload(G[(S + 3) % PG]);
       };
       int mb = m0;
       for (; mb + PER <= m1; mb += PER) static_for<PER>([&](auto sc) { advance(sc); });
@@ -2035,8 +2044,8 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
             return hipErrorInvalidValue;
           const dim3 tb(64 * shape.NW);
           if (B.time_block == 32) {
-            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma<L, 16, 20, 10, 8, DT>), dim3(grid), tb, 0, s, B);
-            else hipLaunchKernelGGL((k_tmfma<L, 16, 20, 10, 4, DT>), dim3(grid), tb, 0, s, B);
+            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma<L, 16, 24, 12, 8, DT>), dim3(grid), tb, 0, s, B);
+            else hipLaunchKernelGGL((k_tmfma<L, 16, 24, 12, 4, DT>), dim3(grid), tb, 0, s, B);
           } else {
             if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma<L, 8, 12, 12, 8, DT>), dim3(grid), tb, 0, s, B);
             else hipLaunchKernelGGL((k_tmfma<L, 8, 12, 12, 4, DT>), dim3(grid), tb, 0, s, B);
