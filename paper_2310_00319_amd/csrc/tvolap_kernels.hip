@@ -1258,8 +1258,8 @@ __global__ __launch_bounds__(64 * NWV) void k_tmfma16(BatchArgs B) {
   constexpr int N = 2 * L;
   constexpr uint32_t RB = 4u * N;           // bytes per row (16-bit complex words)
   constexpr int LS = 4;                     // staging slots per wave
-  constexpr int PER = std::lcm(std::lcm(R, LS), std::lcm(PG, 2));
-  static_assert(R >= NPQ + 2 && PG >= 3, "window and load ring");
+  constexpr int PER = std::lcm(std::lcm(R, LS), std::lcm(PG, 3));
+  static_assert(R >= NPQ + 4 && PG >= 4, "window and load ring");
   __shared__ u4 stage[NWV][LS][64];
   const int TW = B.tile_width;              // 16 bins per wave
   const DevPlan& P = B.P;
@@ -1367,9 +1367,10 @@ __global__ __launch_bounds__(64 * NWV) void k_tmfma16(BatchArgs B) {
     {
       // window of pairs (X_i[c], X_i[c - 1]) by c = q - 2s, X_i[e] = X(block
       // NPQ rowi + e, partition m0): c = NPQ - 1 - 2s .. -2s in use at step s,
-      // -2s - 1 and -2s - 2 read during step s
+      // -2s - 1 and -2s - 2 read during step s - 1, -2s - 3 and -2s - 4 during
+      // step s (two steps ahead of their use)
       uint2 W[R];
-      uint32_t Bq[2][2][2];                 // [step parity][set][partition of the pair]
+      uint32_t Bq[3][2][2];                 // [step mod 3][set][partition of the pair]
       u4 G[PG];
       const int qr = ring_slot(c0 + 2u * (uint32_t)(NPQ * rowi), Mi);
       auto xword = [&](int e) {
@@ -1412,40 +1413,51 @@ __global__ __launch_bounds__(64 * NWV) void k_tmfma16(BatchArgs B) {
 #pragma unroll
       for (int k = 1; k <= PG; ++k) gload(G[k % PG]);
       st[1 * 64 + lane] = G[1];
+      st[2 * 64 + lane] = G[2];
       gload(G[1]);
+      gload(G[2]);
       // piece word index of the lane's operands in a slot
       const int ax0 = 16 * (2 * rowi) + b16;          // X_i[-2k] (value 0), X_i[-2k - 1] at +16
-      // row-step 0's second value, X_i[-1], which step 0 reads from slot 0
-      if ((lane & 3) == rowi) reinterpret_cast<uint32_t*>(stage[w][0])[ax0 + 16] = W[0].y;
       const int bh = 16 * (8 + gl) + b16;             // H: + 32 * set + 64 * partition
+      {
+        // operands of step 1 (row-step 1, partitions m0 + 2, m0 + 3)
+        const uint32_t* sp = stw + 1 * 256;
+        const uint32_t x0 = sp[ax0], x1 = sp[ax0 + 16];
+        W[(R - 1) % R] = make_uint2(W[0].y, x0);
+        W[(R - 2) % R] = make_uint2(x0, x1);
+        const bool on2 = m0 + 2 < m1, on3 = m0 + 3 < m1;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          Bq[1][d][0] = on2 ? barr(sp[bh + 32 * d]) : 0u;
+          Bq[1][d][1] = on3 ? barr(sp[bh + 32 * d + 64]) : 0u;
+        }
+      }
       auto advance = [&](int mm, auto sc, auto tailc) {
         constexpr int S = decltype(sc)::value;       // step index mod PER
-        constexpr bool TAIL = decltype(tailc)::value;
-        // a. operands of row-step s + 1: pairs c = -2s - 1 and -2s - 2, spectra
-        //    of partitions m + 2, m + 3
+        (void)tailc;
+        // a. operands of step s + 2 (row-step s + 2): pairs c = -2s - 3 and
+        //    -2s - 4, spectra of partitions m + 4, m + 5
         {
-          const uint32_t* sp = stw + ((S + 1) % LS) * 256;   // row-step s + 1
-          const uint32_t* sq = stw + (S % LS) * 256;         // row-step s
-          const uint32_t x0 = sp[ax0], x1 = sp[ax0 + 16];      // X_i[-2s - 2], X_i[-2s - 3]
-          const uint32_t xp = sq[ax0 + 16];                    // X_i[-2s - 1]
-          W[(((-2 * S - 1) % R) + R) % R] = make_uint2(xp, x0);
-          W[(((-2 * S - 2) % R) + R) % R] = make_uint2(x0, x1);
-          // partitions past m1: only in the tail, and the second one also in
-          // the last step of a full period (an odd partition count)
-          const bool on2 = !TAIL || mm + 2 < m1;
-          const bool on3 = (!TAIL && S != PER - 1) || mm + 3 < m1;
+          const uint32_t* sp = stw + ((S + 2) % LS) * 256;   // row-step s + 2
+          const uint32_t* sq = stw + ((S + 1) % LS) * 256;   // row-step s + 1
+          const uint32_t x0 = sp[ax0], x1 = sp[ax0 + 16];      // X_i[-2s - 4], X_i[-2s - 5]
+          const uint32_t xp = sq[ax0 + 16];                    // X_i[-2s - 3]
+          W[(((-2 * S - 3) % R) + R) % R] = make_uint2(xp, x0);
+          W[(((-2 * S - 4) % R) + R) % R] = make_uint2(x0, x1);
+          // step s + 2 runs only if m + 4 < m1; its second partition may be m1
+          const bool on5 = mm + 5 < m1;
 #pragma unroll
           for (int d = 0; d < 2; ++d) {
-            const uint32_t h2 = sp[bh + 32 * d], h3 = sp[bh + 32 * d + 64];
-            Bq[(S + 1) & 1][d][0] = on2 ? barr(h2) : 0u;
-            Bq[(S + 1) & 1][d][1] = on3 ? barr(h3) : 0u;
+            const uint32_t h4 = sp[bh + 32 * d], h5 = sp[bh + 32 * d + 64];
+            Bq[(S + 2) % 3][d][0] = barr(h4);
+            Bq[(S + 2) % 3][d][1] = on5 ? barr(h5) : 0u;
           }
         }
         // b. the products of step s
 #pragma unroll
         for (int q = 0; q < NPQ; ++q) {
           const uint2 a = W[(((q - 2 * S) % R) + R) % R];
-          const uint2 b2 = make_uint2(Bq[S & 1][q & 1][0], Bq[S & 1][q & 1][1]);
+          const uint2 b2 = make_uint2(Bq[S % 3][q & 1][0], Bq[S % 3][q & 1][1]);
           if constexpr (DT == 1)
             acc[q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b2),
                                                             acc[q], 0, 0, 0);
@@ -1453,9 +1465,9 @@ __global__ __launch_bounds__(64 * NWV) void k_tmfma16(BatchArgs B) {
             acc[q] = __builtin_amdgcn_mfma_f32_4x4x4f16(__builtin_bit_cast(h4, a), __builtin_bit_cast(h4, b2),
                                                         acc[q], 0, 0, 0);
         }
-        // c. stage row-step s + 2; d. fetch row-step s + 2 + PG
-        st[((S + 2) % LS) * 64 + lane] = G[(S + 2) % PG];
-        gload(G[(S + 2) % PG]);
+        // c. stage row-step s + 3; d. fetch row-step s + 3 + PG
+        st[((S + 3) % LS) * 64 + lane] = G[(S + 3) % PG];
+        gload(G[(S + 3) % PG]);
       };
       int mb = m0;
       for (; mb + 2 * PER <= m1; mb += 2 * PER)
@@ -2019,11 +2031,11 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
             return hipErrorInvalidValue;
           const dim3 tb(64 * shape.NW);
           if (B.time_block == 32) {
-            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma16<L, 8, 10, 10, 8, DT>), dim3(grid), tb, 0, s, B);
-            else hipLaunchKernelGGL((k_tmfma16<L, 8, 10, 10, 4, DT>), dim3(grid), tb, 0, s, B);
+            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma16<L, 8, 12, 12, 8, DT>), dim3(grid), tb, 0, s, B);
+            else hipLaunchKernelGGL((k_tmfma16<L, 8, 12, 12, 4, DT>), dim3(grid), tb, 0, s, B);
           } else {
-            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma16<L, 4, 6, 12, 8, DT>), dim3(grid), tb, 0, s, B);
-            else hipLaunchKernelGGL((k_tmfma16<L, 4, 6, 12, 4, DT>), dim3(grid), tb, 0, s, B);
+            if (shape.NW == 8) hipLaunchKernelGGL((k_tmfma16<L, 4, 8, 12, 8, DT>), dim3(grid), tb, 0, s, B);
+            else hipLaunchKernelGGL((k_tmfma16<L, 4, 8, 12, 4, DT>), dim3(grid), tb, 0, s, B);
           }
           e = hipGetLastError();
           if (e != hipSuccess) return e;
