@@ -191,6 +191,36 @@ def head_bus_accuracy(wl, buses, got, budget_s: float) -> dict:
             "snr_db": {"min": round(float(snr.min()), 2), "max": round(float(snr.max()), 2)}}
 
 
+def practical_hbm_rates(mib: int = 1024, reps: int = 10) -> dict:
+    """What plain streaming kernels reach on this GPU, for context beside the
+    8 TB/s peak: torch's device copy (read + write) and a full sum (read), over
+    a MIB-MiB float32 buffer, timed with events on torch's stream."""
+    import torch
+    a = torch.ones(mib * (1 << 18), device="cuda")
+    b = torch.empty_like(a)
+    nbytes = a.numel() * 4
+    b.copy_(a)
+    s = a.sum()
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        b.copy_(a)
+    e[1].record()
+    for _ in range(reps):
+        s = a.sum()
+    e[2].record()
+    torch.cuda.synchronize()
+    copy_ms = e[0].elapsed_time(e[1]) / reps
+    read_ms = e[1].elapsed_time(e[2]) / reps
+    del a, b, s
+    torch.cuda.empty_cache()
+    return {"torch_copy_gbs": round(2 * nbytes / (copy_ms * 1e-3) / 1e9, 1),
+            "torch_sum_gbs": round(nbytes / (read_ms * 1e-3) / 1e9, 1),
+            "buffer_mib": mib, "note": "torch copy_ (bytes read + written) and sum (bytes read) of one buffer; "
+                                       "context only, the roofline peak stays 8 TB/s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,8 +241,8 @@ def main():
                     help="blocks per call (1 = strict streaming, one block per call; >1 = batched calls)")
     ap.add_argument("--bchunk", type=int, default=0, help="batched MAC: partitions per work item")
     ap.add_argument("--bvec", type=int, default=0, help="batched MAC: complex bins per lane (1 or 2)")
-    ap.add_argument("--bwaves", type=int, default=0, help="batched MAC: waves per workgroup (1, 2 or 4)")
-    ap.add_argument("--btb", type=int, default=0, help="batched MAC: blocks per time group (8 or 16)")
+    ap.add_argument("--bwaves", type=int, default=0, help="batched MAC: waves per workgroup (1, 2, 4 or 8)")
+    ap.add_argument("--btb", type=int, default=0, help="batched MAC: blocks per time group (8, 16 or 32)")
     ap.add_argument("--bgroup", type=int, default=0, help="batched MAC: channels per work item (1 or 2)")
     ap.add_argument("--bengine", type=int, default=0,
                     help="batched MAC engine: 1 = vector ALU, 2 = matrix cores (f32 spectra)")
@@ -535,6 +565,11 @@ def run(args, spec, wl, stream):
                 "phase_us_per_block": {"in": round(1e3 * timing["ms_in"] / timing["blocks"], 3),
                                        "mac": round(1e3 * mac_ms, 3),
                                        "out": round(1e3 * timing["ms_out"] / timing["blocks"], 3)}}
+
+    if roof is not None and roof["bound"] == "hbm":
+        roof["hbm_practical"] = practical_hbm_rates()
+        rd = roof["hbm_practical"]["torch_sum_gbs"]
+        roof["hbm_practical"]["frac_of_torch_sum"] = round(roof["achieved"] / rd, 4) if rd > 0 else None
 
     cpu = None
     accuracy = None

@@ -65,8 +65,14 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         cmds.append([cc, *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", o])
     jobs = jobs or max(1, min(len(cmds), (os.cpu_count() or 2) - 1))
     with ThreadPoolExecutor(jobs) as ex:
-        for f in [ex.submit(_run, c, verbose) for c in cmds]:
-            f.result()
+        futs = [(c, ex.submit(_run, c, verbose)) for c in cmds]
+    failed = [c for c, f in futs if f.exception() is not None]
+    # the device compiler has aborted now and then under a full parallel
+    # load; a unit that failed is compiled once more on its own, and a
+    # second failure is reported
+    for c in failed:
+        print("retrying alone: " + os.path.basename(c[-1]), file=sys.stderr, flush=True)
+        _run(c, verbose)
     tmp = LIB + ".tmp"
     _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

@@ -399,7 +399,7 @@ __device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __
 }
 
 // Inverse real DFT of the packed spectrum Y (eq. 9): the 4L samples of the
-// block's output go to dst.
+// block's output go to dst (16-byte aligned), four per store.
 template <int L, int T>
 __device__ __forceinline__ void inverse_store(float2* Y, float2* bufA, float2* bufB, const float2* twl,
                                               float* __restrict__ dst, int tid) {
@@ -410,9 +410,9 @@ __device__ __forceinline__ void inverse_store(float2* Y, float2* bufA, float2* b
   const float2* R = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
   constexpr float scale = 1.0f / (float)(4 * L);
 #pragma unroll
-  for (int n = tid; n < 4 * L; n += T) {
-    const float2 z = R[n >> 1];
-    dst[n] = ((n & 1) ? -z.y : z.x) * scale;
+  for (int n4 = tid; n4 < L; n4 += T) {
+    const float2 z0 = R[2 * n4], z1 = R[2 * n4 + 1];
+    reinterpret_cast<float4*>(dst)[n4] = make_float4(z0.x * scale, -z0.y * scale, z1.x * scale, -z1.y * scale);
   }
 }
 
@@ -1548,6 +1548,10 @@ __global__ __launch_bounds__(256) void k_bus_sum(BatchArgs B) {
   }
 }
 
+__device__ __forceinline__ float4 add4(float4 a, float4 b) {
+  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+
 // Block j, channel c of a batch: the sum of the channel's partial rows (all
 // partitions, eq. 8) and the inverse transform (eq. 9) into the block buffer.
 template <int L>
@@ -1571,26 +1575,29 @@ __global__ __launch_bounds__(256) void k_batch_inv(BatchArgs B, int bpw) {
     const int j = blockIdx.y * bpw + u;
     if (j >= B.n_blocks) break;
     const float2* yp = B.ypart + (int64_t)j * B.n_rows * TW;
-    for (int k = tid; k < N; k += T) {
+    // two bins per thread (tile widths are even: both lie in one tile row)
+    for (int k = 2 * tid; k < N; k += 2 * T) {
       const int t = k / TW;
       const int kk = k - t * TW;
-      float2 acc = make_float2(0.f, 0.f);
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
       for (int qc = c0; qc < c1; ++qc) {
         const int c = P.out_ch[qc];
         const int nrow = B.nchunks[c];
         const int nch = B.bus_rows ? 1 : nrow;
-        const float2* src = yp + ((int64_t)B.row_base[c] + (int64_t)t * nrow) * TW + kk;
-        float2 s0 = src[0];
-        float2 s1 = make_float2(0.f, 0.f);
+        const float4* src = reinterpret_cast<const float4*>(yp + ((int64_t)B.row_base[c] + (int64_t)t * nrow) * TW + kk);
+        const int64_t rs = TW / 2;   // row stride in float4
+        float4 s0 = src[0];
+        float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f);
         int q = 1;
         for (; q + 1 < nch; q += 2) {
-          s0 = cadd(s0, src[(int64_t)q * TW]);
-          s1 = cadd(s1, src[(int64_t)(q + 1) * TW]);
+          s0 = add4(s0, src[(int64_t)q * rs]);
+          s1 = add4(s1, src[(int64_t)(q + 1) * rs]);
         }
-        if (q < nch) s0 = cadd(s0, src[(int64_t)q * TW]);
-        acc = (qc == c0) ? cadd(s0, s1) : cadd(acc, cadd(s0, s1));
+        if (q < nch) s0 = add4(s0, src[(int64_t)q * rs]);
+        acc = (qc == c0) ? add4(s0, s1) : add4(acc, add4(s0, s1));
       }
-      Y[k] = acc;
+      Y[k] = make_float2(acc.x, acc.y);
+      Y[k + 1] = make_float2(acc.z, acc.w);
     }
     __syncthreads();
     inverse_store<L, T>(Y, bufA, bufB, twl, B.yblk + ((int64_t)j * P.n_out + e) * 4 * L, tid);
@@ -1627,25 +1634,24 @@ __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __r
     const float* yc = B.yblk + (int64_t)c * 4 * L;     // block j at yc + j * n_out * 4L
     const int64_t ystride = (int64_t)P.n_out * 4 * L;
     float* oc = out + (int64_t)c * out_stride;
-    const int t0 = sw * SPW;
-    float v[R];
+    // R consecutive samples per thread, one window of one block (L is a
+    // multiple of R): block and state rows are read R at a time
+    static_assert(L % R == 0, "whole sample groups per window");
+    const int t = sw * SPW + R * tid;
+    if (t < n * L) {
+      const int j = t / L, k = t - j * L;
+      float4 a = (j < 3) ? *reinterpret_cast<const float4*>(st + j * L + k) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int t = t0 + r * T + tid;
-      v[r] = 0.f;
-      if (t < n * L) {
-        const int j = t / L, k = t - j * L;
-        float a = (j < 3) ? st[j * L + k] : 0.f;
-#pragma unroll
-        for (int d = 3; d >= 0; --d)
-          if (j - d >= 0) a += yc[(int64_t)(j - d) * ystride + d * L + k];
-        v[r] = a;
+      for (int d = 3; d >= 0; --d)
+        if (j - d >= 0) a = add4(a, *reinterpret_cast<const float4*>(yc + (int64_t)(j - d) * ystride + d * L + k));
+      if ((reinterpret_cast<uintptr_t>(oc + t) & 15) == 0) {
+        *reinterpret_cast<float4*>(oc + t) = a;
+      } else {
+        oc[t] = a.x;
+        oc[t + 1] = a.y;
+        oc[t + 2] = a.z;
+        oc[t + 3] = a.w;
       }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int t = t0 + r * T + tid;
-      if (t < n * L) oc[t] = v[r];
     }
     // every read of the old state above has returned (its value is stored)
     __syncthreads();
@@ -1677,12 +1683,11 @@ __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __r
         const int u = tid + e * T;
         if (u < 3 * L) st[u] = ns[e];
       }
-      if (tid == 0) {
-        B.arrive[c] = 0;
-        if (B.copy_sel)
-          for (int q = P.out_ptr[c]; q < P.out_ptr[c + 1]; ++q)
-            B.sel_store[P.out_ch[q]] = B.sel[(int64_t)(n - 1) * B.sel_stride + P.out_ch[q]];
-      }
+      if (tid == 0) B.arrive[c] = 0;
+      // slots of the bus's channels at the batch's last block, one channel per thread
+      if (B.copy_sel)
+        for (int q = P.out_ptr[c] + tid; q < P.out_ptr[c + 1]; q += T)
+          B.sel_store[P.out_ch[q]] = B.sel[(int64_t)(n - 1) * B.sel_stride + P.out_ch[q]];
     }
   }
   if (c < P.I && sw == 0) {
@@ -1810,9 +1815,10 @@ __global__ __launch_bounds__(64) void k_inv(DevPlan P, const float2* __restrict_
   }
   __syncthreads();
   inverse_ola<L, 64>(Y, bufA, bufB, twl, old, st, out + (int64_t)e * out_stride, tid);
+  // slots of the bus's channels, one channel per thread
+  if (copy_sel)
+    for (int q = c0 + tid; q < c1; q += 64) sel_store[P.out_ch[q]] = sel[P.out_ch[q]];
   if (tid == 0) {
-    if (copy_sel)
-      for (int q = c0; q < c1; ++q) sel_store[P.out_ch[q]] = sel[P.out_ch[q]];
     if (atomicAdd(done, 1) == (int)gridDim.x - 1) {
       *done = 0;
       *counter = cnt + 1u;
