@@ -537,7 +537,7 @@ __global__ __launch_bounds__(256) void k_batch_spectra(DevPlan P, const float* _
                                                        const float* __restrict__ hist,
                                                        typename Store<DT>::T* __restrict__ fdl,
                                                        const uint64_t* __restrict__ counter, int n_blocks,
-                                                       int32_t* __restrict__ defer_count) {
+                                                       int32_t* __restrict__ defer_count, int bpw) {
   constexpr int N = 2 * L;
   constexpr int T = 256;
   // the matrix-core MAC of this call appends to an empty deferred list
@@ -551,9 +551,9 @@ __global__ __launch_bounds__(256) void k_batch_spectra(DevPlan P, const float* _
   const int Mi = P.in_M[i];
   load_tables<L, T>(P, twl, winl, tid);
   __syncthreads();
-  // kBatchBlocksPerWg consecutive blocks per workgroup (tables loaded once)
-  for (int u = 0; u < kBatchBlocksPerWg; ++u) {
-    const int j = blockIdx.x * kBatchBlocksPerWg + u;
+  // bpw consecutive blocks per workgroup (tables loaded once)
+  for (int u = 0; u < bpw; ++u) {
+    const int j = blockIdx.x * bpw + u;
     if (j >= n_blocks) break;
     const uint64_t cnt = cnt0 + (uint64_t)j;
     const int p = (int)(cnt & 1u);
@@ -2021,8 +2021,11 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
     hipError_t e = hipSuccess;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     const int bgroups = (B.n_blocks + kBatchBlocksPerWg - 1) / kBatchBlocksPerWg;
-    hipLaunchKernelGGL((k_batch_spectra<L, DT>), dim3(bgroups, B.P.I), dim3(256), 0, s, B.P, in, in_stride, hist,
-                       static_cast<ST*>(B.fdl), B.counter, B.n_blocks, B.defer_count);
+    // fewer than 16 workgroups per CU at kBatchBlocksPerWg blocks each: two
+    // blocks per workgroup, for more workgroups in flight
+    const int sbpw = (B.P.I * bgroups < 16 * 256) ? 2 : kBatchBlocksPerWg;
+    hipLaunchKernelGGL((k_batch_spectra<L, DT>), dim3((B.n_blocks + sbpw - 1) / sbpw, B.P.I), dim3(256), 0, s, B.P,
+                       in, in_stride, hist, static_cast<ST*>(B.fdl), B.counter, B.n_blocks, B.defer_count, sbpw);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
