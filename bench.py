@@ -568,8 +568,6 @@ def run(args, spec, wl, stream):
 
     if roof is not None and roof["bound"] == "hbm":
         roof["hbm_practical"] = practical_hbm_rates()
-        rd = roof["hbm_practical"]["torch_sum_gbs"]
-        roof["hbm_practical"]["frac_of_torch_sum"] = round(roof["achieved"] / rd, 4) if rd > 0 else None
 
     cpu = None
     accuracy = None
