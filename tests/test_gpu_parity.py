@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_common import gpu_streams, gpu_streams_graph, log, make_convolver, oracle_streams, rel_rms_per_channel
+from gpu_common import (gpu_streams, gpu_streams_graph, log, make_convolver, oracle_bus_streams, oracle_streams,
+                        rel_rms_per_channel)
 
 pytestmark = pytest.mark.gpu
 
@@ -232,6 +233,52 @@ def test_strided_io_zero_and_short_irs_and_slot_clamp():
         H = orc.channel_spectra([taps.astype(float)], L, int(wl.taps_of_channel[ch]))
         ref = orc.tvolap_stream(xs[ch], H, np.zeros(wl.n_calls, int), L, wl.n_calls)
         assert rel_rms_per_channel(got[ch, :n], ref) <= TOL_F32
+
+
+@pytest.mark.parametrize("engine", [1, 2])
+@pytest.mark.parametrize("mix", [False, True], ids=["channels", "buses"])
+def test_batched_unaligned_strided_io(engine, mix):
+    """Batched calls on input and output rows that start 4 and 12 bytes past a
+    16-byte boundary, with row strides that are not multiples of four samples
+    (the overlap-add then stores sample by sample): bitwise equal to the same
+    calls on contiguous tensors, within the FP32 bar of the oracle, and
+    nothing is written outside the output view."""
+    import torch
+    L = 128
+    wl = synth.random_small(seed=91, hop=L, n_channels=6, n_inputs=3, n_samples=L * 40 + 7,
+                            taps_range=(200, 3000), n_slots=2, p_switch=0.5)
+    buses = np.array([0, 1, 1, 0, 1, 0], np.int32) if mix else None
+    log(f"batched unaligned io, engine {engine}, buses {mix}")
+    n = wl.n_calls * L
+    x = torch.from_numpy(wl.padded_input()).cuda()
+    sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
+
+    def run(aligned: bool) -> np.ndarray:
+        conv = make_convolver(wl, buses=buses)
+        conv.configure_batch(engine=engine)
+        E = conv.n_outputs
+        if aligned:
+            out = torch.zeros((E, n), device="cuda")
+            conv.process(x, sched, out, batch=16)
+            torch.cuda.synchronize()
+            res = out.cpu().numpy()
+        else:
+            xbig = torch.zeros((wl.n_inputs, n + 11), device="cuda")
+            xbig[:, 3:3 + n] = x
+            obig = torch.full((E, n + 9), 7.0, device="cuda")
+            conv.process(xbig[:, 3:3 + n], sched, obig[:, 1:1 + n], batch=16)
+            torch.cuda.synchronize()
+            big = obig.cpu().numpy()
+            assert np.all(big[:, 0] == 7.0) and np.all(big[:, 1 + n:] == 7.0)
+            res = big[:, 1:1 + n]
+        conv.close()
+        return res
+
+    ref_al = run(True)
+    got = run(False)
+    assert np.array_equal(got, ref_al)
+    ref = oracle_bus_streams(wl, buses) if mix else oracle_streams(wl)
+    assert rel_rms_per_channel(got.astype(np.float64), ref).max() <= TOL_F32
 
 
 # ------------------------------------------------------------------ full-size workloads
