@@ -117,3 +117,33 @@ def test_product_path_does_not_reference_the_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".h", ".hpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), f
+
+
+def test_build_retries_a_failed_unit_once_then_reports(monkeypatch, tmp_path):
+    """build(): a unit whose compile fails under the parallel pass is compiled
+    once more on its own; a unit that fails twice raises."""
+    from paper_2310_00319_amd import build as b
+    calls = []
+
+    def fake_run(cmd, verbose):
+        calls.append(cmd[-1])
+        name = os.path.basename(cmd[-1])
+        if name == "tvolap_capi.o" and calls.count(cmd[-1]) == 1:
+            raise RuntimeError("device compiler aborted")
+        if name == "tvolap_dispatch.o" and fail_twice:
+            raise RuntimeError("bad source")
+
+    monkeypatch.setattr(b, "_run", fake_run)
+    monkeypatch.setattr(b, "OBJ", str(tmp_path / "obj"))
+    monkeypatch.setattr(b, "LIB", str(tmp_path / "lib.so"))
+    monkeypatch.setattr(b.os, "replace", lambda a, c: None)
+    fail_twice = False
+    b.build(jobs=2)
+    capi = [c for c in calls if c.endswith("tvolap_capi.o")]
+    assert len(capi) == 2                                     # failed once, retried alone
+    assert calls[-1].endswith("lib.so.tmp")                   # then linked
+    calls.clear()
+    fail_twice = True
+    with pytest.raises(RuntimeError, match="bad source"):
+        b.build(jobs=2)
+    assert not any(c.endswith("lib.so.tmp") for c in calls)  # no link after a second failure
