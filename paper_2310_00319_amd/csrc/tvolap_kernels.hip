@@ -1615,13 +1615,18 @@ __global__ __launch_bounds__(256) void k_batch_inv(BatchArgs B, int bpw) {
 // before it arrives, so nothing waits and the old state is never overwritten
 // early. Workgroups with s = 0 also store the input history (rows c < I) and
 // the selection; the last workgroup of the grid advances the call count by n.
+// Output samples per thread of the batched overlap-add (two 4-sample loads
+// per row in flight per thread).
+constexpr int kOlaSamplesPerThread = 8;
+
 template <int L>
 __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __restrict__ in, int64_t in_stride,
                                                    float* __restrict__ hist, float* __restrict__ ola,
                                                    float* __restrict__ out, int64_t out_stride) {
   constexpr int T = 256;
-  constexpr int R = 4;                     // samples per thread
-  constexpr int SPW = R * T;               // samples per workgroup
+  constexpr int R = 4;                     // samples per load
+  constexpr int V = kOlaSamplesPerThread / R;   // loads per thread and row
+  constexpr int SPW = kOlaSamplesPerThread * T;  // samples per workgroup
   const DevPlan& P = B.P;
   const int c = blockIdx.x, sw = blockIdx.y, tid = threadIdx.x;
   const int n = B.n_blocks;
@@ -1634,10 +1639,12 @@ __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __r
     const float* yc = B.yblk + (int64_t)c * 4 * L;     // block j at yc + j * n_out * 4L
     const int64_t ystride = (int64_t)P.n_out * 4 * L;
     float* oc = out + (int64_t)c * out_stride;
-    // R consecutive samples per thread, one window of one block (L is a
-    // multiple of R): block and state rows are read R at a time
+    // V groups of R consecutive samples per thread, each within one window
+    // (L is a multiple of R): block and state rows are read R at a time
     static_assert(L % R == 0, "whole sample groups per window");
-    const int t = sw * SPW + R * tid;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+    const int t = sw * SPW + R * (v * T + tid);
     if (t < n * L) {
       const int j = t / L, k = t - j * L;
       float4 a = (j < 3) ? *reinterpret_cast<const float4*>(st + j * L + k) : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1652,6 +1659,7 @@ __global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __r
         oc[t + 2] = a.z;
         oc[t + 3] = a.w;
       }
+    }
     }
     // every read of the old state above has returned (its value is stored)
     __syncthreads();
@@ -2115,7 +2123,7 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int wgs = B.P.n_out > B.P.I ? B.P.n_out : B.P.I;
-    const int spw = (B.n_blocks * L + 4 * 256 - 1) / (4 * 256);   // 4 samples per thread, 256 threads
+    const int spw = (B.n_blocks * L + kOlaSamplesPerThread * 256 - 1) / (kOlaSamplesPerThread * 256);
     hipLaunchKernelGGL((k_batch_ola<L>), dim3(wgs, spw), dim3(256), 0, s, B, in, in_stride, hist, B.ola_state, out,
                        out_stride);
     e = hipGetLastError();
