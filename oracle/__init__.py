@@ -7,9 +7,8 @@ Python binding never import, call or link it; it shares no code with them.
 Pins: every function here is checked in ``tests/test_oracle_pins.py`` against
 results fixed by the paper or by mathematics independent of this code
 (brute-force linear convolution, the time-domain block definition, a closed
-form for IR switching, hand-worked examples, finite differences). The one
-function without such a pin is ``quantized_tvolap_streams`` beyond its
-rounding primitive, whose header says "parity unpinned" for the parts not
-covered.
+form for IR switching, hand-worked examples, finite differences, an O(n^2)
+DFT route with its own rounding for the reduced-precision form); the module
+header of ``tvolap_ref`` names the pin of each function.
 """
 from .tvolap_ref import *  # noqa: F401,F403

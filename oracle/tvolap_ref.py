@@ -35,11 +35,23 @@ Readings where the paper is silent, ambiguous or self-inconsistent:
            transform takes the Hermitian extension and ignores the imaginary
            parts at k = 0 and k = 2L.
 
-Pins: every function is checked by tests against results fixed independently
-of this module (brute-force convolution, a time-domain block definition, a
-closed-form cross-fade, hand-worked goldens, a naive DFT, finite differences),
-except ``quantized_tvolap_streams``: parity unpinned as a whole (its rounding
-step ``quantize`` is pinned; the rest is the pinned streaming oracle).
+Pins (tests/test_oracle_pins.py; each reaches the result by another road):
+  hann_window                        half-angle form sin^2, overlap-sum one
+  partition_*/input_*/spectral_mac/
+  inverse_blocks/overlap_add/
+  tvolap_stream/tvolap_offline       brute-force linear convolution (one IR),
+                                     the time-domain block definition and the
+                                     closed-form tap-phase cross-fade (any
+                                     schedule), the polarity-switch curve of
+                                     Sec. 3 (Fig. 3), hand-worked L = 2 goldens
+  numpy.fft as the DFT primitive     an O(n^2) DFT loop
+  tvolap_adjoint                     central finite differences (the MSE loss
+                                     is exactly quadratic)
+  quantize                           hand-checked round-to-nearest-even cases
+  quantized_tvolap_streams           an independent route: O(n^2) DFTs, a
+                                     separately written significand rounding,
+                                     the eq. 8 sum as plain loops, an O(n^2)
+                                     inverse and a time-domain overlap-add
 """
 from __future__ import annotations
 
@@ -48,9 +60,8 @@ import numpy as np
 __all__ = [
     "hann_window", "num_partitions", "partition_ir", "partition_spectra",
     "channel_spectra", "input_blocks", "input_spectra", "spectral_mac",
-    "inverse_blocks", "overlap_add", "tvolap_stream", "tvolap_streams",
+    "inverse_blocks", "overlap_add", "tvolap_stream",
     "tvolap_offline", "tvolap_adjoint", "quantize", "quantized_tvolap_streams",
-    "pack_half_spectrum", "unpack_half_spectrum",
 ]
 
 
@@ -181,19 +192,6 @@ def tvolap_stream(x: np.ndarray, Hsets: np.ndarray, schedule: np.ndarray, L: int
     return overlap_add(y, L, n_calls * L)
 
 
-def tvolap_streams(x: np.ndarray, input_of_channel, Hsets_per_channel: list, schedule: np.ndarray,
-                   L: int, n_calls: int) -> np.ndarray:
-    """Multichannel streaming output [C][n_calls*L]: channel c filters input
-    x[input_of_channel[c]] with its own IR sets ``Hsets_per_channel[c]``
-    ([K][M_c][2L+1]) under ``schedule[:, c]``."""
-    C = len(Hsets_per_channel)
-    out = np.zeros((C, n_calls * L))
-    for c in range(C):
-        out[c] = tvolap_stream(x[int(input_of_channel[c])], Hsets_per_channel[c],
-                               schedule[:, c], L, n_calls)
-    return out
-
-
 def tvolap_offline(x: np.ndarray, Hsets: np.ndarray, schedule: np.ndarray, L: int) -> np.ndarray:
     """One channel, whole signal: y(t) for t in [0, N). ``schedule`` has one
     entry per block l = -1 .. ceil(N/L) - 1 (length ceil(N/L) + 1)."""
@@ -298,12 +296,12 @@ def quantize(a: np.ndarray, dtype: str) -> np.ndarray:
 
 def quantized_tvolap_streams(x, input_of_channel, Hsets_per_channel, schedule, L, n_calls,
                              dtype: str) -> np.ndarray:
-    """As ``tvolap_streams`` but with the stored spectra rounded to ``dtype``:
+    """Multichannel streaming output [C][n_calls*L] with the stored spectra
+    rounded to ``dtype``: channel c filters x[input_of_channel[c]] with its IR
+    sets ``Hsets_per_channel[c]`` ([K][M_c][2L+1]) under ``schedule[:, c]``;
     the partition spectra H and the delay-line spectra X are quantized before
-    the MAC of eq. 8, which then runs in float64. The transforms stay float64.
-
-    Parity unpinned as a whole: it is ``tvolap_streams`` with ``quantize``
-    inserted; ``quantize`` itself is pinned."""
+    the MAC of eq. 8, which then runs in float64. The transforms stay float64
+    (reduced-precision storage with full-precision arithmetic)."""
     C = len(Hsets_per_channel)
     out = np.zeros((C, n_calls * L))
     for c in range(C):
@@ -313,26 +311,3 @@ def quantized_tvolap_streams(x, input_of_channel, Hsets_per_channel, schedule, L
         Y = spectral_mac(H, schedule[:, c], X)
         out[c] = overlap_add(inverse_blocks(Y, L), L, n_calls * L)
     return out
-
-
-# ---------------------------------------------------------------- packed half spectrum
-
-def pack_half_spectrum(S: np.ndarray) -> np.ndarray:
-    """Layout helper for comparing against stored spectra: the 2L + 1 bins of a
-    real 4L-point transform as 2L complex values, bin 0 holding
-    (Re S(0), Re S(2L)) and bins 1 .. 2L - 1 unchanged."""
-    S = np.asarray(S)
-    P = S[..., :-1].copy()
-    P[..., 0] = S[..., 0].real + 1j * S[..., -1].real
-    return P
-
-
-def unpack_half_spectrum(P: np.ndarray) -> np.ndarray:
-    """Inverse of ``pack_half_spectrum`` (imaginary parts at k = 0, 2L set to 0)."""
-    P = np.asarray(P)
-    shape = P.shape[:-1] + (P.shape[-1] + 1,)
-    S = np.zeros(shape, dtype=np.complex128)
-    S[..., 1:-1] = P[..., 1:]
-    S[..., 0] = P[..., 0].real
-    S[..., -1] = P[..., 0].imag
-    return S

@@ -17,6 +17,9 @@ by a different road:
   where h_s^(r) keeps the taps d = r (mod 2L) of set s. With one set this is
   plain convolution because the windows sum to one.
 * ``naive_dft``: an O(n^2) DFT loop.
+* ``quantized_stream_naive``: reduced-precision storage (spectra rounded to
+  bf16/f16 before eq. 8) through O(n^2) DFTs and a significand rounding
+  written from the format definitions (``round_significand``).
 """
 from __future__ import annotations
 
@@ -118,3 +121,88 @@ def naive_dft(a: np.ndarray, sign: int = -1) -> np.ndarray:
             acc += a[t] * complex(math.cos(2 * math.pi * t * k / n), sign * math.sin(2 * math.pi * t * k / n))
         out[k] = acc
     return out
+
+
+# ------------------------------------------------------------------ reduced-precision storage
+
+# (significand bits, smallest normal exponent) of the storage formats
+_FORMATS = {"f32": (24, -126), "bf16": (8, -126), "f16": (11, -14)}
+
+
+def round_significand(v: float, bits: int, emin: int) -> float:
+    """v rounded to ``bits`` significant bits, ties to even, with gradual
+    underflow below 2**emin. Written with frexp and exact power-of-two
+    scaling; no float32/float16 casts and no bit patterns."""
+    if v == 0.0 or not math.isfinite(v):
+        return v
+    _, e = math.frexp(v)                    # |v| in [2**(e-1), 2**e)
+    q = 2.0 ** (max(e - 1, emin) - (bits - 1))   # spacing of the format at v
+    r = v / q                               # exact: q is a power of two
+    n = math.floor(r)
+    frac = r - n
+    if frac > 0.5 or (frac == 0.5 and n % 2 == 1):
+        n += 1
+    return n * q
+
+
+def store_round(v: complex, dtype: str) -> complex:
+    """Storage rounding of one complex value, component-wise: bf16 goes through
+    float32 first (the value is a float32 before it is stored), f16 and f32
+    round the float64 value once."""
+    def one(a):
+        if dtype == "bf16":
+            return round_significand(round_significand(a, *_FORMATS["f32"]), *_FORMATS["bf16"])
+        return round_significand(a, *_FORMATS[dtype])
+    return complex(one(v.real), one(v.imag))
+
+
+def quantized_stream_naive(x, sets, schedule, L, n_calls, dtype):
+    """Streaming output of one channel (n_calls * L samples on the axis that
+    starts at t = -L) with stored spectra rounded to ``dtype``: input blocks
+    and partitions transformed by an O(n^2) DFT, both rounded, the eq. 8 sum
+    over partitions as plain loops, an O(n^2) inverse over the Hermitian
+    extension and the 4L-sample outputs added at hop L."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    w = hann_half_amplitude(L)
+    n_taps = max(len(s) for s in sets)
+    M = max(1, -(-n_taps // (2 * L)))
+    B = 2 * L + 1
+
+    def spectrum(seg2L):
+        padded = np.concatenate([np.asarray(seg2L, dtype=np.float64), np.zeros(2 * L)])
+        return naive_dft(padded)[:B]
+
+    def rnd(v):
+        return np.array([store_round(complex(z), dtype) for z in v])
+
+    H = []
+    for s in sets:
+        flat = np.zeros(2 * L * M)
+        flat[: len(s)] = s
+        H.append([rnd(spectrum(flat[2 * L * m: 2 * L * (m + 1)])) for m in range(M)])
+    X = []
+    for b in range(n_calls):                       # block l = b - 1
+        seg = np.zeros(2 * L)
+        for n in range(2 * L):
+            t = (b - 1) * L + n
+            if 0 <= t < N:
+                seg[n] = x[t] * w[n]
+        X.append(rnd(spectrum(seg)))
+    out = np.zeros(n_calls * L + 4 * L)
+    for b in range(n_calls):
+        Y = np.zeros(B, dtype=np.complex128)
+        s = int(schedule[b])
+        for m in range(M):
+            j = b - 2 * m
+            if j < 0:
+                break
+            for k in range(B):
+                Y[k] += H[s][m][k] * X[j][k]
+        for n in range(4 * L):                     # real inverse, 1/4L
+            acc = Y[0].real + Y[B - 1].real * (-1.0) ** n
+            for k in range(1, B - 1):
+                a = 2.0 * math.pi * n * k / (4 * L)
+                acc += 2.0 * (Y[k].real * math.cos(a) - Y[k].imag * math.sin(a))
+            out[b * L + n] += acc / (4 * L)
+    return out[: n_calls * L]

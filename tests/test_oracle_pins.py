@@ -219,7 +219,7 @@ def test_adjoint_matches_central_differences(L, K, n_taps, N):
         checks.append((fd, dx[t]))
     scale = max(abs(a) for _, a in checks)
     for fd, an in checks:
-        assert abs(fd - an) <= 1e-8 * scale + 1e-12
+        assert abs(fd - an) <= 1e-9 * scale
     # the imaginary parts at k = 0 and k = 2L never reach the output
     assert np.max(np.abs(dH[:, :, 0].imag)) == 0.0
     assert np.max(np.abs(dH[:, :, -1].imag)) == 0.0
@@ -247,11 +247,72 @@ def test_quantize_f16_matches_ieee_half():
     assert q[0] == 1.0 and q[1] == 1.0 + 2 ** -9 and q[2] == 65504.0 and q[3] == 2.0 ** -24
 
 
-def test_pack_roundtrip():
-    r = np.random.default_rng(5)
-    x = r.standard_normal((3, 32))
-    S = np.fft.rfft(x, axis=1)
-    assert np.allclose(orc.unpack_half_spectrum(orc.pack_half_spectrum(S)), S, atol=1e-12)
+def test_round_significand_agrees_with_hardware_formats():
+    """The pin's own rounding reproduces IEEE conversions where numpy has them
+    (float32, float16), including ties, subnormals and the largest half."""
+    r = np.random.default_rng(8)
+    vals = list(r.standard_normal(200) * 10.0 ** r.integers(-6, 4, size=200))
+    vals += [1.0 + 2 ** -11, 1.0 + 3 * 2 ** -11, 65504.0, 2.0 ** -24, 3 * 2.0 ** -25, 2.0 ** -14 * 1.5]
+    vals += [1.0 + 2 ** -24, 1.0 + 3 * 2 ** -24, 2.0 ** -149 * 1.5, -(2.0 ** -130) * 1.25]
+    for v in vals:
+        assert pins.round_significand(v, 11, -14) == float(np.float16(v))
+        assert pins.round_significand(v, 24, -126) == float(np.float32(v))
+
+
+QCASES = [(4, 2, 21, 70, "bf16"), (4, 2, 21, 70, "f16"), (8, 3, 40, 110, "bf16"), (8, 3, 40, 110, "f16")]
+
+
+def _qcase(L, K, n_taps, N):
+    r = np.random.default_rng(1000 + 17 * L + K)
+    sets = _random_sets(r, K, n_taps)
+    x = r.standard_normal(N)
+    n_calls = -(-N // L) + 1
+    sched = r.integers(0, K, size=n_calls)
+    return sets, x, sched, n_calls
+
+
+@pytest.mark.parametrize("L,K,n_taps,N,dtype", QCASES)
+def test_quantized_streams_match_independent_route(L, K, n_taps, N, dtype):
+    """Reduced-precision storage: the oracle (numpy.fft spectra rounded by
+    ``quantize``, FP64 MAC) equals the O(n^2) route with its own rounding."""
+    sets, x, sched, n_calls = _qcase(L, K, n_taps, N)
+    got = orc.quantized_tvolap_streams(x[None, :], [0], [sets_spectra(sets, L)], sched[:, None], L, n_calls,
+                                       dtype)[0]
+    ref = pins.quantized_stream_naive(x, sets, sched, L, n_calls, dtype)
+    assert rel_rms(got, ref) < 1e-12
+    # and the rounding is visible: the unrounded stream differs by about one
+    # unit of the format
+    exact = orc.tvolap_stream(x, sets_spectra(sets, L), sched, L, n_calls)
+    assert rel_rms(exact, ref) > {"bf16": 1e-4, "f16": 1e-5}[dtype]
+
+
+def _quantized_mutant(kind, x, sets, sched, L, n_calls, dtype):
+    """A copy of the oracle's reduced-precision steps with one planted mistake."""
+    H = sets_spectra(sets, L)
+    X = orc.input_spectra(orc.input_blocks(x, L, n_calls), L)
+    if kind != "x_unrounded":
+        X = orc.quantize(X, dtype)
+    if kind != "h_unrounded":
+        H = orc.quantize(H, dtype)
+    Y = orc.spectral_mac(H, sched, X)
+    if kind == "round_y":
+        Y = orc.quantize(Y, dtype)
+    if kind == "round_y_not_hx":
+        Y = orc.quantize(orc.spectral_mac(sets_spectra(sets, L), sched,
+                                          orc.input_spectra(orc.input_blocks(x, L, n_calls), L)), dtype)
+    return orc.overlap_add(orc.inverse_blocks(Y, L), L, n_calls * L)
+
+
+@pytest.mark.parametrize("kind", ["x_unrounded", "h_unrounded", "round_y", "round_y_not_hx"])
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_quantized_pin_rejects_planted_mistakes(kind, dtype):
+    L, K, n_taps, N = 4, 2, 21, 70
+    sets, x, sched, n_calls = _qcase(L, K, n_taps, N)
+    ref = pins.quantized_stream_naive(x, sets, sched, L, n_calls, dtype)
+    bad = _quantized_mutant(kind, x, sets, sched, L, n_calls, dtype)
+    assert rel_rms(bad, ref) > 1e-9
+    good = _quantized_mutant("none", x, sets, sched, L, n_calls, dtype)
+    assert rel_rms(good, ref) < 1e-12
 
 
 # ------------------------------------------------------------------ planted mistakes
