@@ -320,6 +320,26 @@ int tvolap_offline_backward(const tvolap_offline_shape* shape, const float* x, c
                             const int32_t* schedule, const float* gy, float* dx, float* dH, void* workspace,
                             int64_t workspace_bytes, void* stream);
 
+/* Working memory of tvolap_offline_forward_noalloc on each GPU (32 MiB). */
+#define TVOLAP_NOALLOC_SCRATCH_BYTES (32LL << 20)
+
+/* tvolap_offline_forward without a workspace and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc. The result equals
+ * tvolap_offline_forward's bit for bit. Its working memory is one static
+ * device array of TVOLAP_NOALLOC_SCRATCH_BYTES per GPU, placed by the loader
+ * and held until the process ends; its address is looked up on the first
+ * call on each device (`stream` must belong to the current device). The
+ * signal is processed in segments of hops sized to that array; each segment
+ * recomputes the input spectra of the 2(M - 1) blocks before it. Every call
+ * on a GPU shares that GPU's array and overwrites it, so calls whose work
+ * overlaps on one GPU (other streams, other host threads) race: order them on
+ * one stream. Errors: EINVAL (as tvolap_offline_forward, or a shape whose
+ * segments of one hop need more than C (2M + 8) 16L > the array's bytes),
+ * EDEVICE. */
+int tvolap_offline_forward_noalloc(const tvolap_offline_shape* shape, const float* x, const float* H,
+                                   const int32_t* schedule, float* y, void* stream);
+
 /* Message describing the last failed offline call of this thread. */
 const char* tvolap_offline_last_error(void);
 

@@ -33,6 +33,7 @@ EXPORTED = (
     "tvolap_capture_begin", "tvolap_capture_end",
     "tvolap_graph_launch", "tvolap_offline_workspace_bytes", "tvolap_offline_ir_spectra",
     "tvolap_offline_forward", "tvolap_offline_backward", "tvolap_offline_last_error",
+    "tvolap_offline_forward_noalloc",
 )
 
 
@@ -151,6 +152,7 @@ def _declare(lib):
     lib.tvolap_offline_ir_spectra.argtypes = [shp, c_vp, c_i32, c_vp, c_vp]
     lib.tvolap_offline_forward.argtypes = [shp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]
     lib.tvolap_offline_backward.argtypes = [shp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]
+    lib.tvolap_offline_forward_noalloc.argtypes = [shp, c_vp, c_vp, c_vp, c_vp, c_vp]
     lib.tvolap_offline_last_error.argtypes = []
     lib.tvolap_offline_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:

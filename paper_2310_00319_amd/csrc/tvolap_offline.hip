@@ -20,7 +20,9 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "../../include/tvolap.h"
 #include "fft_lds.hpp"
@@ -79,15 +81,17 @@ __global__ __launch_bounds__(T) void k_pack(Shape S, const float2* __restrict__ 
     dst[k] = (k == 0) ? make_float2(src[0].x, src[N].x) : src[k];
 }
 
-// X_all[c][b] = packed spectrum of the windowed block b of x[c]
+// Spectra of blocks b = xb0 + blockIdx.x of x[c] (windowed, zero padded,
+// transformed; packed) -> Xbuf[c][b - xb0] (xn rows per channel).
 template <int L>
-__global__ __launch_bounds__(T) void k_spectra(Shape S, const float* __restrict__ x, float2* __restrict__ Xall) {
+__global__ __launch_bounds__(T) void k_spectra(Shape S, const float* __restrict__ x, float2* __restrict__ Xbuf,
+                                               int32_t xb0, int32_t xn) {
   constexpr int N = 2 * L;
   __shared__ float2 twl[2 * N];
   __shared__ float winl[N];
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
-  const int b = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const int b = xb0 + (int)blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
   make_tables<L>(twl, winl, tid);
   __syncthreads();
   const float* xc = x + (int64_t)c * S.N;
@@ -101,29 +105,36 @@ __global__ __launch_bounds__(T) void k_spectra(Shape S, const float* __restrict_
   }
   __syncthreads();
   const float2* Z = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
-  float2* dst = Xall + ((int64_t)c * S.nblk + b) * N;
+  float2* dst = Xbuf + ((int64_t)c * xn + blockIdx.x) * N;
   for (int k = tid; k < N; k += T) dst[k] = fft::real_fwd_post<N>(Z, k, twl);
 }
 
-// y_b = IDFT_4L(sum_m H_{g(b)}(m) X_{b-2m}) -> yb[c][b][4L]
+// y_b = IDFT_4L(sum_m H_{g(b)}(m) X_{b-2m}) for blocks b = bb0 + blockIdx.x ->
+// yb[c][b - bb0][4L]. H is read in the caller's layout [C][K][M][2L+1]; the
+// packed bin 0 product takes Re H(0) and Re H(2L). Xbuf holds the spectra of
+// blocks xb0 .. xb0 + xn - 1 of each channel, which covers every b - 2m >= 0.
 template <int L>
-__global__ __launch_bounds__(T) void k_fwd_blocks(Shape S, const float2* __restrict__ Hp,
-                                                  const float2* __restrict__ Xall, const int32_t* __restrict__ sched,
-                                                  float* __restrict__ yb) {
+__global__ __launch_bounds__(T) void k_fwd_blocks(Shape S, const float2* __restrict__ H,
+                                                  const float2* __restrict__ Xbuf, int32_t xb0, int32_t xn,
+                                                  const int32_t* __restrict__ sched, float* __restrict__ yb,
+                                                  int32_t bb0, int32_t bn) {
   constexpr int N = 2 * L;
   __shared__ float2 twl[2 * N];
   __shared__ float2 Y[N];
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
-  const int b = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const int b = bb0 + (int)blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
   make_tables<L>(twl, nullptr, tid);
   const int s = slot_of(sched, b, c, S.C, S.K);
-  const float2* H = Hp + (((int64_t)c * S.K + s) * S.M) * N;
-  const float2* X = Xall + (int64_t)c * S.nblk * N;
+  const float2* Hc = H + (((int64_t)c * S.K + s) * S.M) * (N + 1);
+  const float2* X = Xbuf + ((int64_t)c * xn - xb0) * N;
   for (int k = tid; k < N; k += T) {
     float2 acc = make_float2(0.f, 0.f);
-    for (int m = 0; m < S.M && b - 2 * m >= 0; ++m)
-      acc = cadd(acc, pmul(H[(int64_t)m * N + k], X[(int64_t)(b - 2 * m) * N + k], k == 0));
+    for (int m = 0; m < S.M && b - 2 * m >= 0; ++m) {
+      const float2* h = Hc + (int64_t)m * (N + 1);
+      const float2 hk = (k == 0) ? make_float2(h[0].x, h[N].x) : h[k];
+      acc = cadd(acc, pmul(hk, X[(int64_t)(b - 2 * m) * N + k], k == 0));
+    }
     Y[k] = acc;
   }
   __syncthreads();
@@ -131,24 +142,27 @@ __global__ __launch_bounds__(T) void k_fwd_blocks(Shape S, const float2* __restr
   __syncthreads();
   const float2* R = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
   constexpr float scale = 1.0f / (float)(4 * L);
-  float* dst = yb + ((int64_t)c * S.nblk + b) * 4 * L;
+  float* dst = yb + ((int64_t)c * bn + blockIdx.x) * 4 * L;
   for (int n = tid; n < 4 * L; n += T) {
     const float2 z = R[n >> 1];
     dst[n] = ((n & 1) ? -z.y : z.x) * scale;
   }
 }
 
-// y[c][t] = sum over the (up to four) blocks whose output covers t
-__global__ __launch_bounds__(T) void k_ola(Shape S, const float* __restrict__ yb, float* __restrict__ y) {
+// y[c][t] for t in [t0, t1) = sum over the (up to four) blocks whose output
+// covers t, oldest first; yb holds blocks bb0 .. bb0 + bn - 1, which covers
+// every block that meets [t0, t1).
+__global__ __launch_bounds__(T) void k_ola(Shape S, const float* __restrict__ yb, int32_t bb0, int32_t bn,
+                                           int64_t t0, int64_t t1, float* __restrict__ y) {
   const int c = blockIdx.y;
   const int L = S.L;
-  for (int64_t t = (int64_t)blockIdx.x * T + threadIdx.x; t < S.N; t += (int64_t)gridDim.x * T) {
+  for (int64_t t = t0 + (int64_t)blockIdx.x * T + threadIdx.x; t < t1; t += (int64_t)gridDim.x * T) {
     const int64_t q = t / L;
     float acc = 0.f;
     for (int64_t b = q - 2; b <= q + 1; ++b) {
       if (b < 0 || b >= S.nblk) continue;
       const int64_t off = t - (b - 1) * L;
-      if (off >= 0 && off < 4 * L) acc += yb[((int64_t)c * S.nblk + b) * 4 * L + off];
+      if (off >= 0 && off < 4 * L) acc += yb[((int64_t)c * bn + (b - bb0)) * 4 * L + off];
     }
     y[(int64_t)c * S.N + t] = acc;
   }
@@ -333,11 +347,67 @@ int64_t workspace_layout(const Shape& S, Workspace* w, char* base) {
   return off;
 }
 
+// Forward over output segments. Segment [Q0, Q1) of hop indices writes the
+// samples [Q0 L, Q1 L) of y; they are covered by blocks [Q0 - 2, Q1 + 2), whose
+// products need spectra from 2(M - 1) blocks earlier. Each sample is summed by
+// one thread in the same order whatever the segment length, so results do not
+// depend on it.
+struct Segment {
+  int32_t bb0, bn, xb0, xn;
+  int64_t t0, t1;
+};
+
+Segment segment(const Shape& S, int64_t Q0, int64_t nq) {
+  const int64_t Q1 = std::min<int64_t>(Q0 + nq, (int64_t)S.nblk - 1);
+  Segment g;
+  const int64_t bb0 = std::max<int64_t>(0, Q0 - 2), bb1 = std::min<int64_t>(S.nblk, Q1 + 2);
+  const int64_t xb0 = std::max<int64_t>(0, bb0 - 2 * ((int64_t)S.M - 1));
+  g.bb0 = (int32_t)bb0;
+  g.bn = (int32_t)(bb1 - bb0);
+  g.xb0 = (int32_t)xb0;
+  g.xn = (int32_t)(bb1 - xb0);
+  g.t0 = Q0 * S.L;
+  g.t1 = std::min<int64_t>(S.N, Q1 * S.L);
+  return g;
+}
+
+// Scratch bytes of segments of nq hop indices: spectra of nq + 4 + 2(M - 1)
+// blocks and 4L output samples of nq + 4 blocks per channel.
+int64_t segment_bytes(const Shape& S, int64_t nq) {
+  const int64_t nb = nq + 4, nx = nb + 2 * ((int64_t)S.M - 1);
+  return align_up((int64_t)S.C * nx * 2 * S.L * 8) + (int64_t)S.C * nb * 4 * S.L * 4;
+}
+
+hipError_t forward_segments(const Shape& S, const float* x, const float2* H, const int32_t* sched, float* y,
+                            float2* Xbuf, float* yb, int64_t nq, hipStream_t st) {
+  return by_hop(S.L, [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    for (int64_t Q0 = 0; Q0 < (int64_t)S.nblk - 1; Q0 += nq) {
+      const Segment g = segment(S, Q0, nq);
+      if (g.t0 >= g.t1) break;
+      const unsigned ola_x = (unsigned)std::min<int64_t>((g.t1 - g.t0 + T - 1) / T, 65535);
+      hipLaunchKernelGGL((k_spectra<L>), dim3(g.xn, S.C), dim3(T), 0, st, S, x, Xbuf, g.xb0, g.xn);
+      hipLaunchKernelGGL((k_fwd_blocks<L>), dim3(g.bn, S.C), dim3(T), 0, st, S, H, Xbuf, g.xb0, g.xn, sched, yb,
+                         g.bb0, g.bn);
+      hipLaunchKernelGGL(k_ola, dim3(ola_x, S.C), dim3(T), 0, st, S, yb, g.bb0, g.bn, g.t0, g.t1, y);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+}
+
 }  // namespace off
 }  // namespace tvx
 
 using tvx::off::Shape;
 using tvx::off::Workspace;
+
+// Working memory of tvolap_offline_forward_noalloc: one array per GPU, placed
+// by the code-object loader and kept until the process ends. Host code never
+// passes the array's name to a kernel: it is the host-side stand-in of the
+// symbol; the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[TVOLAP_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -370,6 +440,27 @@ int prepare(const Shape& S, void* ws, int64_t ws_bytes, Workspace* w) {
   if (!ws) return off_fail(TVOLAP_EINVAL, "workspace is NULL");
   if (ws_bytes < tvx::off::workspace_layout(S, nullptr, nullptr)) return off_fail(TVOLAP_EINVAL, "workspace too small");
   tvx::off::workspace_layout(S, w, static_cast<char*>(ws));
+  return TVOLAP_OK;
+}
+
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device (with it current) and kept per device.
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;
+
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return off_fail(TVOLAP_EDEVICE, hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return off_fail(TVOLAP_EDEVICE, "hipGetSymbolAddress of the static scratch failed");
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
   return TVOLAP_OK;
 }
 
@@ -411,18 +502,8 @@ int tvolap_offline_forward(const tvolap_offline_shape* shape, const float* x, co
   hipStream_t st = static_cast<hipStream_t>(stream);
   Workspace w;
   if (int rc = prepare(S, workspace, workspace_bytes, &w)) return rc;
-  const dim3 gb(S.nblk, S.C);
-  const unsigned rows = (unsigned)((int64_t)S.C * S.K * S.M);
-  const unsigned ola_x = (unsigned)std::min<int64_t>((S.N + tvx::off::T - 1) / tvx::off::T, 65535);
-  const hipError_t e = tvx::off::by_hop(S.L, [&](auto Lc) {
-    constexpr int L = decltype(Lc)::value;
-    using namespace tvx::off;
-    hipLaunchKernelGGL(k_pack, dim3(rows), dim3(T), 0, st, S, reinterpret_cast<const float2*>(H), w.Hp);
-    hipLaunchKernelGGL((k_spectra<L>), gb, dim3(T), 0, st, S, x, w.Xall);
-    hipLaunchKernelGGL((k_fwd_blocks<L>), gb, dim3(T), 0, st, S, w.Hp, w.Xall, schedule, w.blk);
-    hipLaunchKernelGGL(k_ola, dim3(ola_x, S.C), dim3(T), 0, st, S, w.blk, y);
-    return hipGetLastError();
-  });
+  const hipError_t e = tvx::off::forward_segments(S, x, reinterpret_cast<const float2*>(H), schedule, y, w.Xall,
+                                                  w.blk, (int64_t)S.nblk - 1, st);
   if (e != hipSuccess) return off_fail(TVOLAP_EDEVICE, hipGetErrorString(e));
   return TVOLAP_OK;
 }
@@ -448,7 +529,7 @@ int tvolap_offline_backward(const tvolap_offline_shape* shape, const float* x, c
     hipLaunchKernelGGL((k_gspec<L>), gb, dim3(T), 0, st, S, gy, gspec);
     if (dH) {
       // delay line recomputed from x
-      hipLaunchKernelGGL((k_spectra<L>), gb, dim3(T), 0, st, S, x, w.Xall);
+      hipLaunchKernelGGL((k_spectra<L>), gb, dim3(T), 0, st, S, x, w.Xall, 0, S.nblk);
       hipLaunchKernelGGL(k_dH, dim3(rows), dim3(T), 0, st, S, gspec, w.Xall, schedule,
                          reinterpret_cast<float2*>(dH));
     }
@@ -460,6 +541,35 @@ int tvolap_offline_backward(const tvolap_offline_shape* shape, const float* x, c
     }
     return hipGetLastError();
   });
+  if (e != hipSuccess) return off_fail(TVOLAP_EDEVICE, hipGetErrorString(e));
+  return TVOLAP_OK;
+}
+
+int tvolap_offline_forward_noalloc(const tvolap_offline_shape* shape, const float* x, const float* H,
+                                   const int32_t* schedule, float* y, void* stream) {
+  Shape S;
+  if (int rc = check_shape(shape, &S)) return rc;
+  if (!x || !H || !y) return off_fail(TVOLAP_EINVAL, "x, H or y is NULL");
+  const int64_t cap = TVOLAP_NOALLOC_SCRATCH_BYTES;
+  if (tvx::off::segment_bytes(S, 1) > cap)
+    return off_fail(TVOLAP_EINVAL,
+                    "shape too large for the static scratch: one hop per segment needs C (2M + 8) 16L bytes, "
+                    "more than TVOLAP_NOALLOC_SCRATCH_BYTES");
+  // the longest segment that fits
+  int64_t lo = 1, hi = (int64_t)S.nblk - 1;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (tvx::off::segment_bytes(S, mid) <= cap) lo = mid; else hi = mid - 1;
+  }
+  const int64_t nq = lo;
+  void* base = nullptr;
+  if (int rc = scratch_address(&base)) return rc;
+  const int64_t nx = nq + 4 + 2 * ((int64_t)S.M - 1);
+  float2* Xbuf = static_cast<float2*>(base);
+  float* yb = reinterpret_cast<float*>(static_cast<char*>(base) +
+                                       tvx::off::align_up((int64_t)S.C * nx * 2 * S.L * 8));
+  const hipError_t e = tvx::off::forward_segments(S, x, reinterpret_cast<const float2*>(H), schedule, y, Xbuf, yb,
+                                                  nq, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return off_fail(TVOLAP_EDEVICE, hipGetErrorString(e));
   return TVOLAP_OK;
 }

@@ -106,3 +106,20 @@ def tvolap(x: torch.Tensor, H: torch.Tensor, hop: int, schedule: torch.Tensor | 
     partition spectra H [C][K][M][2L+1] under schedule [nblk][C] (set per
     block, nblk = ceil(N/L) + 1; None = set 0)."""
     return _Tvolap.apply(x, H, schedule, int(hop))
+
+
+def forward_noalloc(x: torch.Tensor, H: torch.Tensor, hop: int, schedule: torch.Tensor | None = None,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """The forward of ``tvolap`` through the library's allocation-free entry
+    point (its working memory is a static per-GPU array; no workspace). With
+    ``out`` given the call allocates nothing at all, so it may run under HIP
+    graph capture. Not differentiable."""
+    shape = _shape(x, H, hop)
+    y = torch.empty_like(x) if out is None else out
+    if y.shape != x.shape or y.dtype != torch.float32 or not y.is_cuda or not y.is_contiguous():
+        raise ValueError("out must be a contiguous CUDA float32 tensor shaped like x")
+    check_offline(load().tvolap_offline_forward_noalloc(
+        ctypes.byref(shape), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(H.data_ptr()),
+        _sched_ptr(schedule, shape), ctypes.c_void_p(y.data_ptr()),
+        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return y
