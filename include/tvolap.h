@@ -217,7 +217,9 @@ int tvolap_configure(tvolap_t* h, int32_t fused, int32_t chunk, int32_t waves, i
  * fastest, caches it for handles of the same shape in this process, and then
  * resets the stream state as tvolap_reset does. *best_us (may be NULL)
  * receives the best time per block in microseconds, or -1 when the choice came
- * from the cache. Synchronous. Errors: EINVAL, ESTATE during capture, EDEVICE. */
+ * from the cache. Synchronous. Errors: EINVAL, ESTATE during capture, EDEVICE;
+ * after an error past the argument checks the previous schedule is applied
+ * again and the stream state is reset (the timed blocks have advanced it). */
 int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us);
 
 /* Schedule of batched calls (tvolap_process_blocks; no effect on results
@@ -247,10 +249,12 @@ int tvolap_configure_batch(tvolap_t* h, int32_t chunk, int32_t vec, int32_t wave
 /* Autotuner for batched calls: times `iters` calls of max_batch blocks (zero
  * input, current bank, block b of the batch in slot b mod K) for each
  * candidate (engine, group, time_block, vec, waves, chunk), keeps the fastest, caches it for handles of
- * the same shape and max_batch in this process, then resets the stream state
- * as tvolap_reset does. *best_us (may be NULL) receives the best time per
- * block in microseconds, or -1 when the choice came from the cache.
- * Synchronous. Errors: EINVAL, ESTATE during capture, EDEVICE. */
+ * the same shape, slot count and max_batch in this process, then resets the stream state
+ * as tvolap_reset does. The selection (tvolap_select_ir) is kept. *best_us
+ * (may be NULL) receives the best time per block in microseconds, or -1 when
+ * the choice came from the cache. Synchronous. Errors: EINVAL, ESTATE during
+ * capture, ENOMEM, EDEVICE; after an error past the argument checks the
+ * previous schedule is applied again and the stream state is reset. */
 int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us);
 
 /* HIP graph capture of the handle's stream (which must not be the null
@@ -342,6 +346,55 @@ int tvolap_offline_forward_noalloc(const tvolap_offline_shape* shape, const floa
 
 /* Message describing the last failed offline call of this thread. */
 const char* tvolap_offline_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * The comparison algorithms of Sec. 3, offline over whole signals (for the
+ * switching and cost comparisons of Figs. 3-5 and Tables 1-2): block
+ * convolution by overlap-add (OLA) and overlap-save (OLS) with block B =
+ * N_IR, weighted overlap-add (WOLA, hop B/2) with an analysis and a synthesis
+ * window, all with 2B-point transforms; and two or more direct time-domain
+ * convolutions cross-faded at the output (CF-TDC). Channel c filters
+ * x[c][0 .. N) with its K responses taps[c][s][0 .. n_taps); the response
+ * active in block b is schedule[b][c] (values clamped into [0, K); NULL =
+ * response 0 throughout). Block grids: OLA block b takes x[bB, (b+1)B) and adds
+ * 2B output samples at bB; OLS block b transforms x[(b-1)B, (b+1)B) and keeps
+ * the last B samples as y[bB, (b+1)B); WOLA block b (b = 0, 1, ...) weights
+ * x[(b-1)R, (b-1)R + B) (R = B/2) with the analysis window and adds, weighted
+ * by the synthesis window, its output at (b-1)R: a rectangular synthesis
+ * keeps all 2B samples, a square-root Hann synthesis weights the first B and
+ * drops the rest. Windows are periodic of length B: Hann (1 - cos(2 pi n/B))/2,
+ * square-root Hann sin(pi n/B). y is aligned with x (no block delay). Device
+ * arrays; work on `stream`, asynchronous. Errors: EINVAL, EDEVICE; message in
+ * tvolap_cmp_last_error(). */
+typedef enum { TVOLAP_CMP_OLA = 0, TVOLAP_CMP_OLS = 1, TVOLAP_CMP_WOLA = 2 } tvolap_cmp_method;
+typedef enum { TVOLAP_WIN_RECT = 0, TVOLAP_WIN_HANN = 1, TVOLAP_WIN_SQRT_HANN = 2 } tvolap_window;
+typedef struct {
+  int32_t method;       /* tvolap_cmp_method                                   */
+  int32_t block;        /* B = 128, 256, 512, 1024 or 2048                     */
+  int32_t n_channels;   /* C, 1 .. 65535                                       */
+  int32_t n_slots;      /* K >= 1 responses per channel                        */
+  int64_t n_samples;    /* N >= 1                                              */
+  int32_t n_taps;       /* response length, 1 .. B                             */
+  int32_t analysis;     /* WOLA: TVOLAP_WIN_HANN or TVOLAP_WIN_SQRT_HANN         */
+  int32_t synthesis;    /* WOLA: TVOLAP_WIN_RECT or TVOLAP_WIN_SQRT_HANN         */
+} tvolap_cmp_shape;
+
+/* Rows of the schedule (blocks of the method's grid), or -1 for a bad shape. */
+int64_t tvolap_cmp_blocks(const tvolap_cmp_shape* shape);
+/* Device workspace bytes of tvolap_cmp_forward, or -1 for a bad shape. */
+int64_t tvolap_cmp_workspace_bytes(const tvolap_cmp_shape* shape);
+/* y = method(x, taps, schedule). */
+int tvolap_cmp_forward(const tvolap_cmp_shape* shape, const float* x, const float* taps, const int32_t* schedule,
+                       float* y, void* workspace, int64_t workspace_bytes, void* stream);
+/* CF-TDC: y(t) = sum_s c_s(t) (x * h_s)(t) with direct convolutions (FP32
+ * sums) and c_s(t) = sum over blocks l = -1, 0, ... with schedule[l + 1][c] =
+ * s of w(t - lL), w the Hann window of length 2L (amplitude 1/2): a Hann
+ * cross-fade of L samples at every switch, on TVOLAP's block grid of hop L
+ * (ceil(N/L) + 1 schedule rows). taps [C][K][n_taps]; any hop >= 1. */
+int tvolap_cftdc_forward(int32_t hop, int32_t n_channels, int32_t n_slots, int64_t n_samples, int32_t n_taps,
+                         const float* x, const float* taps, const int32_t* schedule, float* y, void* stream);
+/* Message describing the last failed comparison call of this thread. */
+const char* tvolap_cmp_last_error(void);
 
 /* Message describing the last error of `h`, or of the last failed
  * tvolap_create when h is NULL. Never NULL. */

@@ -33,7 +33,8 @@ EXPORTED = (
     "tvolap_capture_begin", "tvolap_capture_end",
     "tvolap_graph_launch", "tvolap_offline_workspace_bytes", "tvolap_offline_ir_spectra",
     "tvolap_offline_forward", "tvolap_offline_backward", "tvolap_offline_last_error",
-    "tvolap_offline_forward_noalloc",
+    "tvolap_offline_forward_noalloc", "tvolap_cmp_blocks", "tvolap_cmp_workspace_bytes", "tvolap_cmp_forward",
+    "tvolap_cftdc_forward", "tvolap_cmp_last_error",
 )
 
 
@@ -44,6 +45,19 @@ class TvolapOfflineShape(ctypes.Structure):
         ("n_partitions", ctypes.c_int32),
         ("n_slots", ctypes.c_int32),
         ("n_samples", ctypes.c_int64),
+    ]
+
+
+class TvolapCmpShape(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("n_slots", ctypes.c_int32),
+        ("n_samples", ctypes.c_int64),
+        ("n_taps", ctypes.c_int32),
+        ("analysis", ctypes.c_int32),
+        ("synthesis", ctypes.c_int32),
     ]
 
 
@@ -153,12 +167,22 @@ def _declare(lib):
     lib.tvolap_offline_forward.argtypes = [shp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]
     lib.tvolap_offline_backward.argtypes = [shp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]
     lib.tvolap_offline_forward_noalloc.argtypes = [shp, c_vp, c_vp, c_vp, c_vp, c_vp]
+    cshp = ctypes.POINTER(TvolapCmpShape)
+    lib.tvolap_cmp_blocks.argtypes = [cshp]
+    lib.tvolap_cmp_blocks.restype = c_i64
+    lib.tvolap_cmp_workspace_bytes.argtypes = [cshp]
+    lib.tvolap_cmp_workspace_bytes.restype = c_i64
+    lib.tvolap_cmp_forward.argtypes = [cshp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]
+    lib.tvolap_cftdc_forward.argtypes = [c_i32, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]
+    lib.tvolap_cmp_last_error.argtypes = []
+    lib.tvolap_cmp_last_error.restype = ctypes.c_char_p
     lib.tvolap_offline_last_error.argtypes = []
     lib.tvolap_offline_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         fn = getattr(lib, name)
         if name in ("tvolap_last_error", "tvolap_version", "tvolap_offline_last_error",
-                    "tvolap_offline_workspace_bytes"):
+                    "tvolap_offline_workspace_bytes", "tvolap_cmp_blocks", "tvolap_cmp_workspace_bytes",
+                    "tvolap_cmp_last_error"):
             continue
         fn.restype = c_int
 
@@ -192,3 +216,8 @@ def check(code: int, handle=None):
     if code != TVOLAP_OK:
         msg = load().tvolap_last_error(handle).decode(errors="replace")
         raise TvolapError(code, msg)
+
+
+def check_cmp(code: int):
+    if code != TVOLAP_OK:
+        raise TvolapError(code, load().tvolap_cmp_last_error().decode(errors="replace"))

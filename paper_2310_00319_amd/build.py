@@ -24,6 +24,7 @@ DTYPES = (0, 1, 2)   # f32, bf16, f16 storage
 UNITS = [("tvolap_kernels.hip", [f"-DTVX_HOP={L}", f"-DTVX_DT={d}"], f"tvolap_kernels_L{L}_d{d}.o")
          for L in HOPS for d in DTYPES] + [
     ("tvolap_offline.hip", [], "tvolap_offline.o"),
+    ("tvolap_compare.hip", [], "tvolap_compare.o"),
     ("tvolap_dispatch.cpp", [], "tvolap_dispatch.o"),
     ("tvolap_capi.cpp", [], "tvolap_capi.o"),
 ]

@@ -100,12 +100,18 @@ __device__ __forceinline__ float2* fft_fwd(float2* a, float2* b, const float2* t
     stage<512, 8, 8, T>(b, a, tw, tid); __syncthreads();
     stage<512, 8, 64, T>(a, b, tw, tid); __syncthreads();
     return b;
-  } else {
-    static_assert(N == 1024, "unsupported FFT size");
+  } else if constexpr (N == 1024) {
     stage<1024, 8, 1, T>(a, b, tw, tid); __syncthreads();
     stage<1024, 8, 8, T>(b, a, tw, tid); __syncthreads();
     stage<1024, 4, 64, T>(a, b, tw, tid); __syncthreads();
     stage<1024, 4, 256, T>(b, a, tw, tid); __syncthreads();
+    return a;
+  } else {
+    static_assert(N == 2048, "unsupported FFT size");
+    stage<2048, 8, 1, T>(a, b, tw, tid); __syncthreads();
+    stage<2048, 8, 8, T>(b, a, tw, tid); __syncthreads();
+    stage<2048, 8, 64, T>(a, b, tw, tid); __syncthreads();
+    stage<2048, 4, 512, T>(b, a, tw, tid); __syncthreads();
     return a;
   }
 }

@@ -785,6 +785,9 @@ int enqueue_block(tvolap_t* h, const float* in, int64_t in_stride, float* out, i
   return TVOLAP_OK;
 }
 
+int enqueue_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32_t n_blocks, float* out,
+                   int64_t out_stride, const int32_t* slots_dev, int64_t slots_stride, bool copy_sel);
+
 int reset_state(tvolap_t* h) {
   HIP_TRY(h, tvx::launch_fill_zero(h->d_fdl, (size_t)h->fdl_elems * h->store_bytes, h->stream));
   HIP_TRY(h, tvx::launch_fill_zero(h->d_hist, (size_t)2 * h->I * h->L * sizeof(float), h->stream));
@@ -959,6 +962,17 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   if (out_stride < (int64_t)n_blocks * h->L && h->n_out > 1)
     return fail(h, TVOLAP_EINVAL, "out_stride smaller than n_blocks * hop");
   if (slots_dev && slots_stride < h->C) return fail(h, TVOLAP_EINVAL, "slots_stride smaller than n_channels");
+  return enqueue_blocks(h, in, in_stride, n_blocks, out, out_stride, slots_dev, slots_stride, slots_dev != nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Enqueue a batched call (arguments already checked). copy_sel: the last
+// block's slots become the handle's selection.
+int enqueue_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32_t n_blocks, float* out,
+                   int64_t out_stride, const int32_t* slots_dev, int64_t slots_stride, bool copy_sel) {
   BatchArgs B;
   B.P = h->plan();
   B.items = h->d_bitems;
@@ -974,7 +988,7 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   B.sel = slots_dev ? slots_dev : h->d_sel;
   B.sel_stride = slots_dev ? slots_stride : 0;
   B.sel_store = h->d_sel;
-  B.copy_sel = slots_dev ? 1 : 0;
+  B.copy_sel = (slots_dev && copy_sel) ? 1 : 0;
   B.ypart = h->d_bypart;
   B.yblk = h->d_yblk;
   B.ola_state = h->d_ola;
@@ -1000,6 +1014,10 @@ int tvolap_process_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32
   if (ts) ts->pending = true;
   return TVOLAP_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int tvolap_reset(tvolap_t* h) {
   if (!h) return TVOLAP_EINVAL;
@@ -1051,7 +1069,7 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
   if (!h) return TVOLAP_EINVAL;
   if (h->capturing) return fail(h, TVOLAP_ESTATE, "cannot autotune during graph capture");
   if (iters < 1) return fail(h, TVOLAP_EINVAL, "iters must be >= 1");
-  const std::string key = "batch/" + std::to_string(h->max_batch) + "/" + tune_key(h);
+  const std::string key = "batch/" + std::to_string(h->max_batch) + "/" + std::to_string(h->K) + "/" + tune_key(h);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_btune_cache.find(key);
@@ -1073,24 +1091,37 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
   std::vector<int> tbs = {8};
   if (nb >= 32) tbs.push_back(16);
   if (nb >= 64) tbs.push_back(32);   // matrix cores only
-  // zero input and scratch output of one full batch, for the timing only
+  // zero input and scratch output of one full batch, for the timing only.
+  // Every exit goes through `finish`: buffers and events are released, and on
+  // an error the schedule in force before the call is applied again.
+  const BatchChoice prev = h->bchoice;
   float* tin = nullptr;
   float* tout = nullptr;
-  HIP_TRY(h, dalloc(&tin, (size_t)h->I * nb * h->L * sizeof(float)));
-  if (dalloc(&tout, (size_t)h->C * nb * h->L * sizeof(float)) != hipSuccess) {
-    dfree(tin);
-    return fail(h, TVOLAP_ENOMEM, "autotuner buffers");
-  }
-  if (tvx::launch_fill_zero(tin, (size_t)h->I * nb * h->L * sizeof(float), h->stream) != hipSuccess) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timing_was = h->timing;
+  auto finish = [&](int rc) {
+    (void)hipStreamSynchronize(h->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     dfree(tin);
     dfree(tout);
-    return fail(h, TVOLAP_EDEVICE, "autotuner buffers");
-  }
+    h->timing = timing_was;
+    if (rc != TVOLAP_OK) {
+      const std::string msg = h->err;
+      (void)apply_batch_choice(h, prev);
+      (void)reset_state(h);
+      h->err = msg;
+    }
+    return rc;
+  };
+  if (dalloc(&tin, (size_t)h->I * nb * h->L * sizeof(float)) != hipSuccess ||
+      dalloc(&tout, (size_t)h->C * nb * h->L * sizeof(float)) != hipSuccess)
+    return finish(fail(h, TVOLAP_ENOMEM, "autotuner buffers"));
+  if (tvx::launch_fill_zero(tin, (size_t)h->I * nb * h->L * sizeof(float), h->stream) != hipSuccess)
+    return finish(fail(h, TVOLAP_EDEVICE, "autotuner buffers"));
   const int64_t ist = (int64_t)nb * h->L;
-  hipEvent_t e0, e1;
-  HIP_TRY(h, hipEventCreate(&e0));
-  HIP_TRY(h, hipEventCreate(&e1));
-  const bool timing_was = h->timing;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return finish(fail(h, TVOLAP_EDEVICE, "hipEventCreate"));
   h->timing = false;
   BatchChoice best;
   float best_t = 1e30f;
@@ -1133,12 +1164,13 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
         c.engine = eng;
         rc = apply_batch_choice(h, c);
         if (rc != TVOLAP_OK) break;
-        // every block of the batch selects slot (block mod K), as a switching stream does
-        rc = tvolap_process_blocks(h, tin, ist, nb, tout, ist, h->d_tune_bsel, h->C);
+        // every block of the batch selects slot (block mod K), as a switching
+        // stream does; the handle's own selection is left as it was
+        rc = enqueue_blocks(h, tin, ist, nb, tout, ist, h->d_tune_bsel, h->C, false);
         if (rc != TVOLAP_OK) break;
         if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = fail(h, TVOLAP_EDEVICE, "event record"); break; }
         for (int k = 0; k < iters && rc == TVOLAP_OK; ++k)
-          rc = tvolap_process_blocks(h, tin, ist, nb, tout, ist, h->d_tune_bsel, h->C);
+          rc = enqueue_blocks(h, tin, ist, nb, tout, ist, h->d_tune_bsel, h->C, false);
         if (rc != TVOLAP_OK) break;
         if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
           rc = fail(h, TVOLAP_EDEVICE, "event synchronize");
@@ -1157,14 +1189,9 @@ int tvolap_autotune_batch(tvolap_t* h, int32_t iters, float* best_us) {
     if (rc != TVOLAP_OK) break;
   }
   if (rc == TVOLAP_OK && best_t >= 1e30f) rc = fail(h, TVOLAP_EDEVICE, "autotuner found no candidate");
-  (void)hipStreamSynchronize(h->stream);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  dfree(tin);
-  dfree(tout);
-  h->timing = timing_was;
-  if (rc != TVOLAP_OK) return rc;
-  RC_TRY(apply_batch_choice(h, best));
+  if (rc == TVOLAP_OK) rc = apply_batch_choice(h, best);
+  if (rc != TVOLAP_OK) return finish(rc);
+  (void)finish(TVOLAP_OK);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_btune_cache[key] = best;
@@ -1203,10 +1230,23 @@ int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us) {
     const int S = (int)std::max<int64_t>(2, (units + target - 1) / target);
     if (std::find(chunks.begin(), chunks.end(), S) == chunks.end()) chunks.push_back(S);
   }
-  hipEvent_t e0, e1;
-  HIP_TRY(h, hipEventCreate(&e0));
-  HIP_TRY(h, hipEventCreate(&e1));
+  // on an error the schedule in force before the call is applied again
+  const MacChoice prev = h->choice;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timing_was = h->timing;
+  auto restore = [&](int rc) {
+    (void)hipStreamSynchronize(h->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    h->timing = timing_was;
+    const std::string msg = h->err;
+    (void)apply_choice(h, prev);
+    (void)reset_state(h);
+    h->err = msg;
+    return rc;
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return restore(fail(h, TVOLAP_EDEVICE, "hipEventCreate"));
   h->timing = false;
   MacChoice best;
   float best_t = 1e30f;
@@ -1256,11 +1296,11 @@ int tvolap_autotune(tvolap_t* h, int32_t iters, float* best_us) {
     if (rc != TVOLAP_OK) break;
   }
   if (rc == TVOLAP_OK && best_t >= 1e30f) rc = fail(h, TVOLAP_EDEVICE, "autotuner found no candidate");
+  if (rc == TVOLAP_OK) rc = apply_choice(h, best);
+  if (rc != TVOLAP_OK) return restore(rc);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->timing = timing_was;
-  if (rc != TVOLAP_OK) return rc;
-  RC_TRY(apply_choice(h, best));
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;

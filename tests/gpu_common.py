@@ -22,6 +22,21 @@ def rel_rms_per_channel(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
     return num / np.maximum(den, 1e-300)
 
 
+def max_abs_err_per_channel(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Largest element error of each channel relative to the channel's largest
+    reference magnitude: an element-wise bound that a short burst of wrong
+    samples (a wrong block at a switch) cannot hide in the RMS of the stream."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return np.max(np.abs(got - ref), axis=-1) / np.maximum(np.max(np.abs(ref), axis=-1), 1e-300)
+
+
+# Element-wise bar for FP32 storage: every sample within 1e-4 of the channel's
+# peak (the rel-RMS bar is 1e-5; single samples may sit a few times above the
+# RMS error, never orders of magnitude).
+ELEM_TOL_F32 = 1e-4
+
+
 def oracle_streams(wl, channels=None, dtype: str = "f32") -> np.ndarray:
     """FP64 oracle stream outputs [len(channels)][n_calls*L] of a workload.
     dtype "f32" = exact oracle; "bf16"/"f16" = spectra rounded before the MAC."""
