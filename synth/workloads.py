@@ -13,6 +13,8 @@ Sec. 4 long binaural room responses, multichannel operation at the end of Sec. 2
 * ``binaural``  S sources x 2 ears, white (even sources) / pink (odd sources)
                 noise, K IR slots per ear with RT60 drawn in [0.3, 1.5] s, the
                 active slot advancing every block (head tracking).
+* ``binaural_fresh`` the same sources with K = 64 response sets per ear and
+                block l using set l mod 64: no set recurs within 64 blocks.
 * ``uneven``    C channels with their own white-noise input, IR lengths drawn
                 log-uniform, two slots per channel, each channel toggling its slot
                 with probability 0.1 per block.
@@ -31,7 +33,7 @@ ROLE_INPUT, ROLE_IR, ROLE_SCHED, ROLE_RT60, ROLE_TARGET, ROLE_FD, ROLE_LEN = ran
 __all__ = [
     "SEED_BASE", "ROLE_INPUT", "ROLE_IR", "ROLE_SCHED", "ROLE_RT60", "ROLE_TARGET",
     "ROLE_FD", "ROLE_LEN", "Workload", "rng", "white_noise", "pink_noise",
-    "decaying_ir", "n_calls_for", "plain", "binaural", "uneven", "autograd",
+    "decaying_ir", "fast_decaying_ir", "n_calls_for", "plain", "binaural", "binaural_fresh", "uneven", "autograd",
     "random_small", "PRESETS",
 ]
 
@@ -157,6 +159,41 @@ def binaural(n_sources: int = 64, n_samples: int = 240_000, hop: int = 256,
     n_calls = n_calls_for(n_samples, hop)
     sched = np.repeat((np.arange(n_calls) % n_slots).astype(np.int32)[:, None], C, axis=1)
     return Workload("binaural", cfg, hop, fs, x, inp, taps,
+                    np.full(C, n_taps, np.int32), n_slots, sched)
+
+
+def fast_decaying_ir(n_taps: int, r: np.random.Generator, fs: float, rt60: float) -> np.ndarray:
+    """float32 Gaussian noise under 10**(-3 n / (rt60 fs)), unit L2 norm: the
+    recipe of ``decaying_ir`` drawn in float32, for banks of thousands of
+    responses."""
+    n = np.arange(n_taps, dtype=np.float32)
+    g = r.standard_normal(n_taps, dtype=np.float32)
+    h = g * np.exp(n * np.float32(-3.0 * math.log(10.0) / (rt60 * fs)), dtype=np.float32)
+    return (h / np.float32(np.sqrt(np.sum(h.astype(np.float64) ** 2)))).astype(np.float32)
+
+
+def binaural_fresh(n_sources: int = 64, n_samples: int = 240_000, hop: int = 256, n_taps: int = 96_000,
+                   n_slots: int = 64, fs: int = 48_000, cfg: int = 6, base: Workload | None = None) -> Workload:
+    """Head tracking with a new response set at every block: the binaural
+    sources and ears, K = n_slots response sets per ear (RT60 drawn in
+    [0.3, 1.5] s per set) and block l using set l mod K for every channel, so
+    within K consecutive blocks no set repeats. ``base``: a ``binaural``
+    workload of the same sources whose input signals are reused."""
+    if base is None:
+        base = binaural(n_sources=n_sources, n_samples=n_samples, hop=hop, n_taps=16, n_slots=1, fs=fs)
+    from concurrent.futures import ThreadPoolExecutor
+
+    C = 2 * n_sources
+
+    def ear(c):
+        return [fast_decaying_ir(n_taps, rng(cfg, ROLE_IR, c, k), fs, rng(cfg, ROLE_RT60, c, k).uniform(0.3, 1.5))
+                for k in range(n_slots)]
+
+    with ThreadPoolExecutor(8) as ex:
+        taps = list(ex.map(ear, range(C)))
+    n_calls = n_calls_for(n_samples, hop)
+    sched = np.repeat((np.arange(n_calls) % n_slots).astype(np.int32)[:, None], C, axis=1)
+    return Workload("binaural_fresh", cfg, hop, fs, base.x, base.input_of_channel, taps,
                     np.full(C, n_taps, np.int32), n_slots, sched)
 
 
