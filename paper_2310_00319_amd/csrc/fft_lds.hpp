@@ -116,6 +116,60 @@ __device__ __forceinline__ float2* fft_fwd(float2* a, float2* b, const float2* t
   }
 }
 
+// The same stages with a twiddle table of the transform's own length:
+// tw[t] = exp(-2 pi i t / N) for t < N. The table of a 4L-point transform is
+// the real-transform table of hop L, so a workgroup holding that table can
+// run one complex 4L-point transform of two real signals at once.
+template <int N, int R, int NS, int T>
+__device__ __forceinline__ void stage_nat(const float2* __restrict__ src, float2* __restrict__ dst,
+                                          const float2* __restrict__ tw, int tid) {
+  constexpr int NB = N / R;
+  constexpr int TWS = N / (NS * R);
+#pragma unroll
+  for (int j0 = 0; j0 < NB; j0 += T) {
+    const int j = j0 + tid;
+    if ((NB % T == 0) || j < NB) {
+      const int k = j & (NS - 1);
+      float2 v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[j + r * NB];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * TWS]);
+      }
+      dft<R>(v);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[base + r * NS] = v[r];
+    }
+  }
+}
+template <int N, int T>
+__device__ __forceinline__ float2* fft_nat(float2* a, float2* b, const float2* tw, int tid) {
+  if constexpr (N == 256) {
+    stage_nat<256, 8, 1, T>(a, b, tw, tid); __syncthreads();
+    stage_nat<256, 8, 8, T>(b, a, tw, tid); __syncthreads();
+    stage_nat<256, 4, 64, T>(a, b, tw, tid); __syncthreads();
+    return b;
+  } else if constexpr (N == 512) {
+    stage_nat<512, 8, 1, T>(a, b, tw, tid); __syncthreads();
+    stage_nat<512, 8, 8, T>(b, a, tw, tid); __syncthreads();
+    stage_nat<512, 8, 64, T>(a, b, tw, tid); __syncthreads();
+    return b;
+  } else if constexpr (N == 1024) {
+    stage_nat<1024, 8, 1, T>(a, b, tw, tid); __syncthreads();
+    stage_nat<1024, 8, 8, T>(b, a, tw, tid); __syncthreads();
+    stage_nat<1024, 4, 64, T>(a, b, tw, tid); __syncthreads();
+    stage_nat<1024, 4, 256, T>(b, a, tw, tid); __syncthreads();
+    return a;
+  } else {
+    stage_nat<2048, 8, 1, T>(a, b, tw, tid); __syncthreads();
+    stage_nat<2048, 8, 8, T>(b, a, tw, tid); __syncthreads();
+    stage_nat<2048, 8, 64, T>(a, b, tw, tid); __syncthreads();
+    stage_nat<2048, 4, 512, T>(b, a, tw, tid); __syncthreads();
+    return a;
+  }
+}
 // Packed bin k of the real 2N-point DFT from Z = FFT_N(x(2n) + i x(2n+1)).
 template <int N>
 __device__ __forceinline__ float2 real_fwd_post(const float2* Z, int k, const float2* tw) {

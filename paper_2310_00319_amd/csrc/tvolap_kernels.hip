@@ -108,6 +108,39 @@ __device__ __forceinline__ void load_vec(const typename Store<DT>::T* __restrict
   }
 }
 
+// load_vec with the non-temporal hint: partition spectra are streamed once per
+// block, so they are kept from displacing the delay line (read again two
+// blocks later) in the caches.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nt_u2 __attribute__((ext_vector_type(2)));
+template <int DT, int V>
+__device__ __forceinline__ void load_vec_nt(const typename Store<DT>::T* __restrict__ p, float2 (&o)[V]) {
+  if constexpr (DT == 0 && V % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < V; j += 2) {
+      const nt_f4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p + j));
+      o[j] = make_float2(t.x, t.y);
+      o[j + 1] = make_float2(t.z, t.w);
+    }
+  } else if constexpr (DT != 0 && V == 2) {
+    const nt_u2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_u2*>(p));
+    o[0] = unpack<DT>(t.x);
+    o[1] = unpack<DT>(t.y);
+  } else if constexpr (DT != 0 && V % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < V; j += 4) {
+      const nt_u4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p + j));
+      o[j] = unpack<DT>(t.x);
+      o[j + 1] = unpack<DT>(t.y);
+      o[j + 2] = unpack<DT>(t.z);
+      o[j + 3] = unpack<DT>(t.w);
+    }
+  } else {
+    load_vec<DT, V>(p, o);
+  }
+}
+
 // Device-coherent publication of partial spectra between workgroups of one
 // launch. Relaxed agent-scope atomic stores and loads of the 8-byte values are
 // performed at the device coherence point (they are not kept in, or served
@@ -247,7 +280,7 @@ __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int g = 0; g < G; ++g)
-        if (m + u * NW < Mc[g]) load_vec<DT, V>(hbase[g] + (uint32_t)((m + u * NW) * N + kbase), H[u][g]);
+        if (m + u * NW < Mc[g]) load_vec_nt<DT, V>(hbase[g] + (uint32_t)((m + u * NW) * N + kbase), H[u][g]);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -263,7 +296,7 @@ __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
     for (int g = 0; g < G; ++g) {
       if (m < Mc[g]) {
         float2 H[V];
-        load_vec<DT, V>(hbase[g] + (uint32_t)(m * N + kbase), H);
+        load_vec_nt<DT, V>(hbase[g] + (uint32_t)(m * N + kbase), H);
         accumulate(g, H, X);
       }
     }
@@ -398,6 +431,74 @@ __device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __
   inverse_ola<L, T>(Y, bufA, bufB, twl, old, st, out + (int64_t)c * out_stride, tid);
 }
 
+// Complete channels c0 and c1 together: both spectra, one 4L-point complex
+// inverse transform of Y0 + i Y1 (both outputs are real, so the real part is
+// channel c0's block and the imaginary part channel c1's), overlap-add of both.
+// Ya, Yb: 2L each; F0, F1: 4L each (LDS). twl holds exp(-2 pi i t / 4L).
+template <int L, int T, int DT, bool COHERENT>
+__device__ __forceinline__ void pair_final(const DevPlan& P, const float2* __restrict__ ypart,
+                                           const typename Store<DT>::T* __restrict__ bank,
+                                           const typename Store<DT>::T* __restrict__ fdl,
+                                           const int32_t* __restrict__ sel, int c0, int c1, int p, uint64_t cnt,
+                                           float2* Ya, float2* Yb, float2* F0, float2* F1, const float2* twl,
+                                           float* __restrict__ ola, float* __restrict__ out, int64_t out_stride,
+                                           int tid) {
+  constexpr int N = 2 * L;
+  constexpr int NPT = (4 * L + T - 1) / T;
+  float* st0 = ola + (int64_t)c0 * 3 * L;
+  float* st1 = ola + (int64_t)c1 * 3 * L;
+  float old0[NPT], old1[NPT];
+  ola_prefetch<L, T>(st0, old0, tid);
+  ola_prefetch<L, T>(st1, old1, tid);
+  channel_spectrum<L, T, DT, COHERENT>(P, ypart, bank, fdl, sel, c0, p, cnt, Ya, tid);
+  channel_spectrum<L, T, DT, COHERENT>(P, ypart, bank, fdl, sel, c1, p, cnt, Yb, tid);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int k = tid + j * T;
+    if (k < 4 * L) {
+      float2 y0, y1;
+      if (k == 0) {
+        y0 = make_float2(Ya[0].x, 0.f);
+        y1 = make_float2(Yb[0].x, 0.f);
+      } else if (k == N) {
+        y0 = make_float2(Ya[0].y, 0.f);
+        y1 = make_float2(Yb[0].y, 0.f);
+      } else if (k < N) {
+        y0 = Ya[k];
+        y1 = Yb[k];
+      } else {
+        y0 = fft::cconj(Ya[4 * L - k]);
+        y1 = fft::cconj(Yb[4 * L - k]);
+      }
+      F0[k] = make_float2(y0.x - y1.y, -(y0.y + y1.x));
+    }
+  }
+  __syncthreads();
+  const float2* R = fft::fft_nat<4 * L, T>(F0, F1, twl, tid);
+  constexpr float scale = 1.0f / (float)(4 * L);
+  float* o0 = out + (int64_t)c0 * out_stride;
+  float* o1 = out + (int64_t)c1 * out_stride;
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int n = tid + j * T;
+    if (n < 4 * L) {
+      const float2 z = R[n];
+      const float v0 = z.x * scale, v1 = -z.y * scale;
+      if (n < L) {
+        o0[n] = old0[j] + v0;
+        o1[n] = old1[j] + v1;
+      } else if (n < 3 * L) {
+        st0[n - L] = old0[j] + v0;
+        st1[n - L] = old1[j] + v1;
+      } else {
+        st0[n - L] = v0;
+        st1[n - L] = v1;
+      }
+    }
+  }
+}
+
 // Inverse real DFT of the packed spectrum Y (eq. 9): the 4L samples of the
 // block's output go to dst (16-byte aligned), four per store.
 template <int L, int T>
@@ -421,20 +522,29 @@ __device__ __forceinline__ void inverse_store(float2* Y, float2* bufA, float2* b
 // Work items: kind 1 = new spectrum of one input (placed first), kind 0 = MAC
 // over a partition chunk of up to G channels sharing an input. Every channel
 // waits for needed[c] arrivals (its MAC items plus its input's spectrum item);
-// the item that arrives last completes the channel. No item ever waits.
+// the item that arrives last completes the channel. No item ever waits. An
+// item counts its arrivals for all its channels at once, counts itself done
+// (the last item advances the call counter, which only the next launch reads)
+// and then completes its channels, two at a time with one complex transform.
 template <int L, int V, int G, int NW, int DT>
 __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
   using ST = typename Store<DT>::T;
   constexpr int N = 2 * L;
   constexpr int T = 64 * NW;
   constexpr int TW = 64 * V;
+  // the MAC reduction buffer doubles as the pair completion's 4L-point buffers
+  constexpr int RED = NW * G * TW;
+  constexpr int POOL = RED > 4 * N ? RED : 4 * N;
   __shared__ float2 twl[2 * N];
   __shared__ float winl[N];
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
   __shared__ float2 ybuf[N];
-  __shared__ float2 red[NW][G][TW];
-  __shared__ int flag;
+  __shared__ float2 pool[POOL];
+  __shared__ int cand[4];
+  __shared__ int won[4];
+  __shared__ int nwon;
+  auto red = reinterpret_cast<float2 (*)[G][TW]>(pool);
   const DevPlan& P = A.P;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -447,23 +557,45 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
   // The FFT tables are loaded up front (made visible by the first barrier), so
   // neither spectrum items nor channel completions wait for them later.
   load_tables<L, T>(P, twl, winl, tid);
-  bool tables = true;
 
-  // Count one arrival for channel c; if it was the last one, complete c.
-  auto arrive = [&](int c) {
-    if (tid == 0) flag = (atomicAdd(&A.arrive[c], 1) == A.needed[c] - 1) ? 1 : 0;
+  // Count one arrival for the channel group cand[0 .. n) (set by thread 0;
+  // the channels go through LDS so that the work item stays in registers) and,
+  // if last, the item itself. A group (the channels of an input that share
+  // work items) has one counter, kept under its first channel: every item
+  // publishes all the group's data before it counts, so the arrival that
+  // completes the counter completes every channel of the group, and the
+  // group is always finished the same way (two channels per complex
+  // transform), whichever workgroups arrive last.
+  auto arrive = [&](int n, bool last_of_item) {
+    if (tid == 0) {
+      const int c0 = cand[0];
+      int k = 0;
+      if (atomicAdd(&A.arrive[c0], 1) == A.needed[c0] - 1) {
+        for (int j = 0; j < n; ++j) won[j] = cand[j];
+        k = n;
+      }
+      nwon = k;
+      if (last_of_item && atomicAdd(A.done, 1) == A.n_items - 1) {
+        // every item has started, so every workgroup has read the call count
+        *A.done = 0;
+        *A.counter = cnt + 1u;
+      }
+    }
     __syncthreads();
-    if (flag) {
-      if (!tables) {
-        load_tables<L, T>(P, twl, winl, tid);
-        tables = true;
-      }
-      channel_final<L, T, DT, true>(P, A.ypart, bank, fdl, A.sel, c, p, cnt, ybuf, bufA, bufB, twl, A.ola, A.out,
-                                    A.out_stride, tid);
-      if (tid == 0) {
-        A.arrive[c] = 0;
-        if (A.copy_sel) A.sel_store[c] = A.sel[c];
-      }
+    const int k = nwon;
+    for (int j = 0; j < k; j += 2) {
+      if (j + 1 < k)
+        pair_final<L, T, DT, true>(P, A.ypart, bank, fdl, A.sel, won[j], won[j + 1], p, cnt, bufA, bufB, pool,
+                                   pool + 2 * N, twl, A.ola, A.out, A.out_stride, tid);
+      else
+        channel_final<L, T, DT, true>(P, A.ypart, bank, fdl, A.sel, won[j], p, cnt, ybuf, bufA, bufB, twl, A.ola,
+                                      A.out, A.out_stride, tid);
+      __syncthreads();
+    }
+    if (tid < k) {
+      const int c = won[tid];
+      if (tid == 0) A.arrive[c] = 0;
+      if (A.copy_sel) A.sel_store[c] = A.sel[c];
     }
     __syncthreads();
   };
@@ -471,17 +603,19 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
   for (int idx = blockIdx.x; idx < A.n_items; idx += gridDim.x) {
     const WorkItem it = A.items[idx];
     if (it.kind == 1) {
-      if (!tables) {
-        load_tables<L, T>(P, twl, winl, tid);
-        tables = true;
-        __syncthreads();
-      }
       if (inl) {
         input_spectrum<L, T, DT, true>(P, A.in, A.in_stride, A.hist, fdl, it.input, p, cnt, twl, winl, bufA, bufB,
                                        tid);
         wait_memory();
         __syncthreads();
-        for (int j = P.in_ch_ptr[it.input]; j < P.in_ch_ptr[it.input + 1]; ++j) arrive(P.in_ch[j]);
+        // the input's channels in groups of G, as the work items group them
+        const int j1 = P.in_ch_ptr[it.input + 1];
+        for (int j = P.in_ch_ptr[it.input]; j < j1; j += G) {
+          const int n = min(G, j1 - j);
+          if (tid == 0)
+            for (int q = 0; q < n; ++q) cand[q] = P.in_ch[j + q];
+          arrive(n, j + G >= j1);
+        }
       } else {
         input_spectrum<L, T, DT, false>(P, A.in, A.in_stride, A.hist, fdl, it.input, p, cnt, twl, winl, bufA, bufB,
                                         tid);
@@ -490,31 +624,24 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
       }
     } else {
       float2 acc[G][V];
-      // two partitions in flight per wave keep the fused kernel within 128
-      // VGPRs, so two 8-wave workgroups (e.g. a spectrum item next to a MAC
-      // item) fit on one compute unit
+      // two partitions in flight per wave keep the streaming loop well within
+      // the register budget
       mac_item<V, G, NW, DT, 2>(P, it, bank, fdl, A.sel, p, cnt, lane, w, acc);
       if (inl) {
         write_partials<V, G, NW, true>(it, acc, red, A.ypart, lane, w, tid);
         wait_memory();
         __syncthreads();
+        if (tid == 0) {
 #pragma unroll
-        for (int g = 0; g < G; ++g)
-          if (g < it.n_ch) arrive(it.ch[g]);
+          for (int g = 0; g < G; ++g) cand[g] = it.ch[g];
+        }
+        arrive(it.n_ch, true);
       } else {
         write_partials<V, G, NW, false>(it, acc, red, A.ypart, lane, w, tid);
         __syncthreads();
         continue;
       }
     }
-    if (tid == 0) {
-      if (atomicAdd(A.done, 1) == A.n_items - 1) {
-        // every item has finished, so every workgroup has read the call count
-        *A.done = 0;
-        *A.counter = cnt + 1u;
-      }
-    }
-    __syncthreads();
   }
 }
 
