@@ -348,6 +348,52 @@ int tvolap_offline_forward_noalloc(const tvolap_offline_shape* shape, const floa
 const char* tvolap_offline_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * Non-uniform partitions (Sec. 1 names uniform and non-uniform partitioning;
+ * Sec. 2's time-variant method applied to each part): a head of M1 short
+ * partitions at hop L1 (latency 2 L1) covers taps [0, D), D = 2 L1 M1, and a
+ * tail of long partitions at hop L2 = r L1 covers taps [D, max_taps), its
+ * output joining D samples later. y(t) = y_head(t) + y_tail(t - D), each part
+ * a TVOLAP output on its own block grid (switches fade over L1 in the head,
+ * over L2 in the tail). Tail block l2 starts contributing where head block
+ * r l2 + 2 M1 does and takes that block's selection; it is computed in the
+ * same call, once every r calls, which needs M1 >= r - 1. With r = 1 the
+ * result is uniform TVOLAP at hop L1. The stream is y delayed by L1. */
+typedef struct tvolap_nup tvolap_nup_t;
+typedef struct {
+  tvolap_config base;        /* hop = L1; max_taps = N_IR; taps_of_channel must be
+                                NULL and n_outputs 0; max_batch is not used        */
+  int32_t tail_ratio;        /* r: power of two, r L1 in {64, 128, 256, 512}        */
+  int32_t head_partitions;   /* M1 >= max(1, r - 1)                               */
+} tvolap_nup_config;
+
+/* Create: two TVOLAP handles (head and tail) on base.stream plus an input ring
+ * and a tail output stage. Errors: EINVAL, ENOMEM, EDEVICE. */
+int tvolap_nup_create(const tvolap_nup_config* cfg, tvolap_nup_t** out);
+int tvolap_nup_destroy(tvolap_nup_t* h);
+/* As tvolap_set_ir: taps [0, D) go to the head, taps [D, n_taps) to the tail. */
+int tvolap_nup_set_ir(tvolap_nup_t* h, int32_t channel, int32_t slot, const float* taps, int32_t n_taps,
+                      int32_t taps_on_device);
+/* As tvolap_select_ir, for both parts. */
+int tvolap_nup_select_ir(tvolap_nup_t* h, const int32_t* slot_of_channel);
+/* One call of L1 new samples per input (as tvolap_process_block); every r
+ * calls it also runs the tail's block. slot_of_channel_dev (device [C] or
+ * NULL) is this call's selection; the tail takes the latest one. */
+int tvolap_nup_process_block(tvolap_nup_t* h, const float* in, int64_t in_stride, float* out, int64_t out_stride,
+                             const int32_t* slot_of_channel_dev);
+int tvolap_nup_reset(tvolap_nup_t* h);
+/* Autotune both parts (tvolap_autotune), then reset. */
+int tvolap_nup_autotune(tvolap_nup_t* h, int32_t iters);
+/* Graph capture of the shared stream. The calls are issued with host-side
+ * positions in the input ring, so a graph must start at a call count that is
+ * a multiple of the period P (tvolap_nup_period) and hold a multiple of P
+ * calls; replays then continue the stream. */
+int tvolap_nup_period(const tvolap_nup_t* h);
+int tvolap_nup_capture_begin(tvolap_nup_t* h);
+int tvolap_nup_capture_end(tvolap_nup_t* h);
+int tvolap_nup_graph_launch(tvolap_nup_t* h);
+const char* tvolap_nup_last_error(const tvolap_nup_t* h);
+
+/* ------------------------------------------------------------------------
  * The comparison algorithms of Sec. 3, offline over whole signals (for the
  * switching and cost comparisons of Figs. 3-5 and Tables 1-2): block
  * convolution by overlap-add (OLA) and overlap-save (OLS) with block B =

@@ -9,6 +9,8 @@ results fixed by the paper or by mathematics independent of this code
 (brute-force linear convolution, the time-domain block definition, a closed
 form for IR switching, hand-worked examples, finite differences, an O(n^2)
 DFT route with its own rounding for the reduced-precision form); the module
-header of ``tvolap_ref`` names the pin of each function.
+header of ``tvolap_ref`` names the pin of each function. ``comparators_ref``
+(the comparison algorithms of Sec. 3) and ``nup_ref`` (non-uniform
+partitions) are submodules with their own pins, named in their headers.
 """
 from .tvolap_ref import *  # noqa: F401,F403

@@ -35,6 +35,9 @@ EXPORTED = (
     "tvolap_offline_forward", "tvolap_offline_backward", "tvolap_offline_last_error",
     "tvolap_offline_forward_noalloc", "tvolap_cmp_blocks", "tvolap_cmp_workspace_bytes", "tvolap_cmp_forward",
     "tvolap_cftdc_forward", "tvolap_cmp_last_error",
+    "tvolap_nup_create", "tvolap_nup_destroy", "tvolap_nup_set_ir", "tvolap_nup_select_ir",
+    "tvolap_nup_process_block", "tvolap_nup_reset", "tvolap_nup_autotune", "tvolap_nup_period",
+    "tvolap_nup_capture_begin", "tvolap_nup_capture_end", "tvolap_nup_graph_launch", "tvolap_nup_last_error",
 )
 
 
@@ -75,6 +78,14 @@ class TvolapConfig(ctypes.Structure):
         ("max_batch", ctypes.c_int32),
         ("n_outputs", ctypes.c_int32),
         ("output_of_channel", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class TvolapNupConfig(ctypes.Structure):
+    _fields_ = [
+        ("base", TvolapConfig),
+        ("tail_ratio", ctypes.c_int32),
+        ("head_partitions", ctypes.c_int32),
     ]
 
 
@@ -174,6 +185,19 @@ def _declare(lib):
     lib.tvolap_cmp_workspace_bytes.restype = c_i64
     lib.tvolap_cmp_forward.argtypes = [cshp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]
     lib.tvolap_cftdc_forward.argtypes = [c_i32, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]
+    lib.tvolap_nup_create.argtypes = [ctypes.POINTER(TvolapNupConfig), ctypes.POINTER(c_vp)]
+    lib.tvolap_nup_destroy.argtypes = [c_vp]
+    lib.tvolap_nup_set_ir.argtypes = [c_vp, c_i32, c_i32, c_vp, c_i32, c_i32]
+    lib.tvolap_nup_select_ir.argtypes = [c_vp, c_vp]
+    lib.tvolap_nup_process_block.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i64, c_vp]
+    lib.tvolap_nup_reset.argtypes = [c_vp]
+    lib.tvolap_nup_autotune.argtypes = [c_vp, c_i32]
+    lib.tvolap_nup_period.argtypes = [c_vp]
+    lib.tvolap_nup_capture_begin.argtypes = [c_vp]
+    lib.tvolap_nup_capture_end.argtypes = [c_vp]
+    lib.tvolap_nup_graph_launch.argtypes = [c_vp]
+    lib.tvolap_nup_last_error.argtypes = [c_vp]
+    lib.tvolap_nup_last_error.restype = ctypes.c_char_p
     lib.tvolap_cmp_last_error.argtypes = []
     lib.tvolap_cmp_last_error.restype = ctypes.c_char_p
     lib.tvolap_offline_last_error.argtypes = []
@@ -182,7 +206,7 @@ def _declare(lib):
         fn = getattr(lib, name)
         if name in ("tvolap_last_error", "tvolap_version", "tvolap_offline_last_error",
                     "tvolap_offline_workspace_bytes", "tvolap_cmp_blocks", "tvolap_cmp_workspace_bytes",
-                    "tvolap_cmp_last_error"):
+                    "tvolap_cmp_last_error", "tvolap_nup_last_error"):
             continue
         fn.restype = c_int
 
@@ -221,3 +245,8 @@ def check(code: int, handle=None):
 def check_cmp(code: int):
     if code != TVOLAP_OK:
         raise TvolapError(code, load().tvolap_cmp_last_error().decode(errors="replace"))
+
+
+def check_nup(code: int, handle=None):
+    if code != TVOLAP_OK:
+        raise TvolapError(code, load().tvolap_nup_last_error(handle).decode(errors="replace"))

@@ -25,6 +25,7 @@ UNITS = [("tvolap_kernels.hip", [f"-DTVX_HOP={L}", f"-DTVX_DT={d}"], f"tvolap_ke
          for L in HOPS for d in DTYPES] + [
     ("tvolap_offline.hip", [], "tvolap_offline.o"),
     ("tvolap_compare.hip", [], "tvolap_compare.o"),
+    ("tvolap_nup.hip", [], "tvolap_nup.o"),
     ("tvolap_dispatch.cpp", [], "tvolap_dispatch.o"),
     ("tvolap_capi.cpp", [], "tvolap_capi.o"),
 ]
