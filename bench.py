@@ -58,6 +58,10 @@ WORKLOADS = {
                         "each channel toggles with p=0.1 per block, 2 s at 48 kHz", fn="uneven", dtype="f32"),
     "plain": dict(desc="1 channel, L=128, 4096-tap IRs, 2 slots switched every 50 blocks, 10 s at 48 kHz",
                   fn="plain", dtype="f32"),
+    "nup": dict(desc="binaural sources and ears (128 channels), 96000-tap IRs at a 128-sample latency: non-uniform "
+                     "partitions (head hop 64, 7 partitions of 128 taps; tail hop 512, 93 partitions of 1024 taps) "
+                     "against uniform partitions at hop 64 (750 partitions), 4 IR slots switched every block, "
+                     "5 s at 48 kHz", fn="binaural", kw=dict(hop=64), dtype="f32"),
     "autograd": dict(desc="32 channels, L=256, 8192-tap IRs (16 partitions), 2 s at 48 kHz, MSE loss against "
                           "a target made by hidden IRs, gradients for H and x", fn="autograd", dtype="f32"),
 }
@@ -125,16 +129,27 @@ def tmac_unique_bytes(wl, batch: int, store_bytes: int) -> int:
     return total
 
 
-def cpu_baseline(wl, budget_s: float, keep: list | None = None) -> dict:
-    """FP64 oracle on the first channels of the workload until the budget is
-    spent. The outputs of the channels it finished are appended to ``keep``."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def _oracle_channels(wl, channels, budget_s: float, keep: list | None = None):
+    """FP64 oracle streams of `channels` in order until the budget is spent:
+    (channels done, wall s, CPU s)."""
     import oracle as orc
 
     x = wl.padded_input().astype(np.float64)
     t_wall = time.perf_counter()
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     done = 0
-    for c in range(wl.n_channels):
+    for c in channels:
         H = orc.channel_spectra([t.astype(np.float64) for t in wl.taps[c]], wl.hop, int(wl.taps_of_channel[c]))
         y = orc.tvolap_stream(x[wl.input_of_channel[c]], H, wl.schedule[:, c], wl.hop, wl.n_calls)
         if keep is not None:
@@ -144,21 +159,65 @@ def cpu_baseline(wl, budget_s: float, keep: list | None = None) -> dict:
             break
     wall = time.perf_counter() - t_wall
     r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    samples = done * wl.n_calls * wl.hop
-    model = "unknown CPU"
+    return done, wall, (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+
+
+def _oracle_shard(job):
+    """Worker of the multi-core leg (a fresh interpreter: spawned, so it holds
+    no GPU state): regenerate the workload from its seeds, then run the oracle
+    on this worker's channels until the budget is spent."""
+    name, channels, budget_s = job
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    import synth
+    spec = WORKLOADS[name]
+    wl = getattr(synth, spec["fn"])(**spec.get("kw", {}))
+    done, wall, _ = _oracle_channels(wl, channels, budget_s)
+    return done, wall
+
+
+def cpu_baseline(wl, name: str, budget_s: float, keep: list | None = None) -> dict:
+    """The FP64 oracle on the host, two ways: one process on the first channels
+    until the budget is spent (outputs appended to ``keep`` for the accuracy
+    check), and channel shards in one single-threaded process per core of this
+    process's CPU share (at most 16), for the same budget each. value = the
+    multi-core rate."""
+    import multiprocessing as mp
+
+    done, wall, cpu = _oracle_channels(wl, range(wl.n_channels), budget_s, keep)
+    one = done * wl.n_calls * wl.hop / wall
     try:
-        with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return {"value": samples / wall, "unit": "channel-samples/s", "cores": max(1, int(round(cpu / wall))),
-            "kind": "oracle", "cpu": model,
-            "sample": f"FP64 oracle, first {done} of {wl.n_channels} channels over the full "
-                      f"{wl.n_calls}-block stream ({wall:.1f} s wall, {cpu:.1f} s CPU)"}
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    workers = max(1, min(16, share, wl.n_channels))
+    per = [list(range(k, wl.n_channels, workers)) for k in range(workers)]
+    multi = None
+    try:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_shard, [(name, ch, budget_s) for ch in per])
+            span = time.perf_counter() - t0
+        # each worker's rate over its own compute time, summed: the aggregate
+        # rate with every worker busy (generating the inputs is excluded)
+        rate = sum(r[0] * wl.n_calls * wl.hop / max(r[1], 1e-9) for r in res)
+        multi = {"value": rate, "workers": workers, "channels": int(sum(r[0] for r in res)), "wall_s": round(span, 1)}
+    except Exception as e:   # the single-process figure still stands
+        log(f"multi-core oracle leg failed: {e!r}")
+    single = {"value": one, "cores": max(1, int(round(cpu / wall))),
+              "sample": f"first {done} of {wl.n_channels} channels over the full {wl.n_calls}-block stream "
+                        f"({wall:.1f} s wall, {cpu:.1f} s CPU)"}
+    if multi is None:
+        return {"value": one, "unit": "channel-samples/s", "cores": single["cores"], "kind": "oracle",
+                "cpu": _cpu_model(), "host_cpu_count": os.cpu_count(), "cpu_share": share,
+                "sample": "FP64 oracle, one process: " + single["sample"]}
+    return {"value": multi["value"], "unit": "channel-samples/s", "cores": workers, "kind": "oracle",
+            "cpu": _cpu_model(), "host_cpu_count": os.cpu_count(), "cpu_share": share,
+            "sample": (f"FP64 oracle, channel shards in {workers} single-threaded processes for about "
+                       f"{budget_s:.0f} s each ({multi['channels']} channels over the full {wl.n_calls}-block "
+                       f"stream, {multi['wall_s']} s wall with input generation); rate = the sum of the workers' "
+                       "rates"),
+            "single_process": single}
 
 
 def head_bus_accuracy(wl, buses, got, budget_s: float) -> dict:
@@ -221,6 +280,198 @@ def practical_hbm_rates(mib: int = 1024, reps: int = 10) -> dict:
                                        "context only, the roofline peak stays 8 TB/s"}
 
 
+USE_GRAPHS = True   # bench.py --no-graph: issue every call directly (hardware-counter passes)
+
+
+def graph_step_ms(conv, step_fn, steps: int, warmup: int = 1) -> float:
+    """Capture step_fn() once as a HIP graph on the convolver's stream, replay
+    it warmup + steps times and return the milliseconds per replay, from events
+    recorded on that stream (torch's current stream here) around the timed
+    replays. Without graphs (--no-graph) step_fn() itself is timed."""
+    import torch
+    if USE_GRAPHS:
+        conv.capture_begin()
+        step_fn()
+        conv.capture_end()
+        run = conv.graph_launch
+    else:
+        run = step_fn
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def block_roofline(info: dict, us_per_launch: float, case: str) -> dict:
+    """Roofline of the one-block kernel: the spectral MAC's algorithmic bytes of
+    one block (every active partition spectrum and every same-parity
+    delay-line spectrum of each input, once) over the average launch duration,
+    against the 8 TB/s HBM peak."""
+    kbytes = info["mac_bytes_per_block"]
+    gbs = kbytes / (us_per_launch * 1e-6) / 1e9
+    tr = measured_traffic(case)
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": tr[0] if tr else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_source": tr[1] if tr else None,
+            "kernel": "k_block (one launch per block: input spectra, spectral MAC of eq. 8, inverse transform and "
+                      "overlap-add of the channels)",
+            "bytes_per_launch": int(kbytes), "avg_launch_us": round(us_per_launch, 3),
+            "duration_source": "graph replay of one launch per block, HIP events on the launch stream "
+                               "(launch gaps included)"}
+
+
+def streaming_leg(conv, wl, x, sched, out, steps: int, case: str) -> dict:
+    """Strict streaming: one process_block per block (latency 2L), per-block
+    schedule autotuned, the calls of one pass captured as a HIP graph."""
+    tuned = conv.autotune(iters=10)
+    info = conv.info()
+    conv.reset()
+    ms = graph_step_ms(conv, lambda: conv.process(x, sched, out, batch=1), steps)
+    us = 1e3 * ms / wl.n_calls
+    return {"value": round(wl.n_channels * wl.hop / (us * 1e-6), 1), "unit": "channel-samples/s",
+            "us_per_block": round(us, 3), "real_time_factor": round((wl.hop / wl.fs) / (us * 1e-6), 1),
+            "latency_samples": 2 * wl.hop, "graph": True, "steps": steps,
+            "roofline": block_roofline(info, us, case),
+            "schedule": {"chunk": info["mac_chunk"], "waves": info["mac_waves"], "grid": info["mac_grid"],
+                         "work_items": info["n_work_items"], "autotuned_us_per_block": tuned}}
+
+
+def fresh_legs(args, base, stream) -> dict:
+    """Head tracking without recurring response sets: the binaural sources and
+    ears with 64 sets per ear, block l using set l mod 64, so no set repeats
+    within a 64-block call. Three measurements: 64-block calls from a graph,
+    strict streaming (one call per block) from a graph, and strict streaming
+    where every block first loads the next block's set from taps
+    (tvolap_set_irs for all 128 ears, then tvolap_process_block), one graph for
+    the whole pass. The partition spectra are loaded from the same taps in
+    every case, so the three outputs agree."""
+    import torch
+
+    import synth
+    from paper_2310_00319_amd import Convolver
+
+    t0 = time.perf_counter()
+    wl = synth.binaural_fresh(base=base)
+    log(f"fresh response sets generated in {time.perf_counter() - t0:.1f} s: K={wl.n_slots}")
+    C, K, L = wl.n_channels, wl.n_slots, wl.hop
+    conv = Convolver(hop=L, n_channels=C, max_taps=wl.max_taps(), n_inputs=wl.n_inputs,
+                     input_of_channel=wl.input_of_channel, taps_of_channel=wl.taps_of_channel, n_slots=K,
+                     dtype="f32", stream=stream, max_batch=64)
+    # taps of every set resident on the device ([K][C][n]), loaded slot by slot
+    pool = torch.empty((K, C, wl.max_taps()), device="cuda", dtype=torch.float32)
+    for k in range(K):
+        pool[k].copy_(torch.from_numpy(np.stack([wl.taps[c][k] for c in range(C)])))
+        conv.set_irs(k, pool[k])
+    torch.cuda.synchronize()
+    x = torch.from_numpy(wl.padded_input()).cuda()
+    sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
+    out_b = torch.empty((C, wl.n_calls * L), device="cuda")
+    out_s = torch.empty_like(out_b)
+    out_i = torch.empty_like(out_b)
+    steps = max(2, args.steps // 2)
+    res = {"workload": f"binaural, {K} response sets per ear, block l uses set l mod {K} (no set recurs within "
+                       f"{K} blocks)", "ir_sets": K, "bank_bytes": conv.info()["bank_bytes"]}
+    # 64-block calls
+    tuned = conv.autotune_batch(iters=2)
+    info = conv.info()
+    conv.reset()
+    ms = graph_step_ms(conv, lambda: conv.process(x, sched, out_b, batch=64), steps)
+    calls = -(-wl.n_calls // 64)
+    conv.set_timing(True)
+    conv.get_timing()
+    conv.process(x, sched, out_b, batch=64)
+    tm = conv.get_timing()
+    conv.set_timing(False)
+    mac_us = 1e3 * tm["ms_mac"] / calls
+    kbytes = tmac_unique_bytes(wl, 64, 8) / calls
+    gbs = kbytes / (mac_us * 1e-6) / 1e9
+    mfma = info["batch_engine"] == 2
+    res["blocks_per_call_64"] = {
+        "value": round(C * wl.n_calls * L / (ms * 1e-3), 1), "unit": "channel-samples/s",
+        "us_per_block": round(1e3 * ms / wl.n_calls, 3), "buffering_ms": round(1e3 * 64 * L / wl.fs, 1),
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "batched spectral MAC of eq. 8 (" + ("matrix-core engine with its vector-ALU units" if mfma
+                                                                    else "k_tmac, vector ALU") + ")",
+                     "bytes_per_launch": int(kbytes), "avg_launch_us": round(mac_us, 3),
+                     "bytes_note": "unique bytes of a call: the partition spectra of all 64 sets once, the delay-line "
+                                   "spectra the call's blocks reach once per input and parity"},
+        "phase_us_per_block": {"in": round(1e3 * tm["ms_in"] / tm["blocks"], 3),
+                               "mac": round(1e3 * tm["ms_mac"] / tm["blocks"], 3),
+                               "out": round(1e3 * tm["ms_out"] / tm["blocks"], 3)},
+        "schedule": {"engine": {1: "vector ALU", 2: "matrix cores"}[info["batch_engine"]],
+                     "time_block": info["batch_time_block"], "chunk": info["batch_chunk"],
+                     "autotuned_us_per_block": tuned}}
+    # one block per call
+    conv.reset()
+    res["one_block_per_call"] = streaming_leg(conv, wl, x, sched, out_s, steps, "binaural_fresh stream k_block")
+    # one block per call, each preceded by loading the next block's set from taps
+    conv.reset()
+
+    def ingest_pass():
+        for c in range(wl.n_calls):
+            k = c % K
+            conv.set_irs(k, pool[k])
+            conv.process_block(x[:, c * L:(c + 1) * L], out_i[:, c * L:(c + 1) * L], sched[c])
+
+    ms_i = graph_step_ms(conv, ingest_pass, steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(K):
+        conv.set_irs(k, pool[k])
+    e1.record()
+    torch.cuda.synchronize()
+    us_set = 1e3 * e0.elapsed_time(e1) / K
+    us_i = 1e3 * ms_i / wl.n_calls
+    parts = info["sum_partitions"]
+    res["one_block_per_call_with_taps_every_block"] = {
+        "value": round(C * L / (us_i * 1e-6), 1), "unit": "channel-samples/s", "us_per_block": round(us_i, 3),
+        "real_time_factor": round((L / wl.fs) / (us_i * 1e-6), 1),
+        "ingest_us_per_block": round(us_set, 2), "ingest_share": round(us_set / us_i, 3),
+        "ingest_partition_transforms_per_s": round(parts / (us_set * 1e-6), 1),
+        "note": "per block: tvolap_set_irs (partition, zero pad, transform and store the 24064 partition spectra "
+                "of the next set from device taps [128][96000]) then tvolap_process_block; the whole pass is one "
+                "captured graph"}
+    # agreement of the three paths (the same taps and schedule)
+    conv.reset()
+    conv.process(x, sched, out_b, batch=64)
+    conv.reset()
+    conv.process(x, sched, out_s, batch=1)
+    conv.reset()
+    if USE_GRAPHS:
+        conv.graph_launch()                   # the ingest pass
+    else:
+        ingest_pass()
+    torch.cuda.synchronize()
+    ob, os_, oi = out_b.double(), out_s.double(), out_i.double()
+    res["ingest_equals_prebanked_bitwise"] = bool(torch.equal(out_i, out_s))
+    res["batched_vs_one_block_max_rel_rms"] = float(f"{float(((ob - os_).norm(dim=1) / os_.norm(dim=1)).max()):.3e}")
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        xs = wl.padded_input().astype(np.float64)
+        errs = []
+        for c in (0, C - 1):
+            H = orc.channel_spectra([t.astype(np.float64) for t in wl.taps[c]], L, int(wl.taps_of_channel[c]))
+            ref = orc.tvolap_stream(xs[wl.input_of_channel[c]], H, wl.schedule[:, c], L, wl.n_calls)
+            for o in (ob, os_):
+                g = o[c].cpu().numpy()
+                errs.append(float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
+        res["accuracy"] = {"vs": "FP64 oracle", "channels": [0, C - 1], "max_rel_rms": float(f"{max(errs):.3e}")}
+    conv.close()
+    del pool
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +498,10 @@ def main():
     ap.add_argument("--bengine", type=int, default=0,
                     help="batched MAC engine: 1 = vector ALU, 2 = matrix cores (f32 spectra)")
     ap.add_argument("--no-ingest", action="store_true", help="skip the IR-bank ingestion timing")
+    ap.add_argument("--fresh-only", action="store_true",
+                    help="only the legs with 64 response sets per ear (binaural)")
+    ap.add_argument("--no-fresh", action="store_true",
+                    help="skip the legs with 64 response sets per ear (no set recurs within 64 blocks)")
     ap.add_argument("--no-realtime", action="store_true",
                     help="skip the extra one-block-per-call measurement")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
@@ -273,6 +528,8 @@ def main():
     import synth
     from paper_2310_00319_amd import Convolver
 
+    global USE_GRAPHS
+    USE_GRAPHS = args.graph
     spec = WORKLOADS[args.workload]
     log(f"workload {args.workload}: {spec['desc']}")
     t0 = time.perf_counter()
@@ -284,7 +541,99 @@ def main():
     with torch.cuda.stream(stream):
         if args.workload == "autograd":
             return run_autograd(args, spec, wl)
+        if args.workload == "nup":
+            return run_nup(args, spec, wl, stream)
+        if args.fresh_only:
+            fresh = fresh_legs(args, wl, stream)
+            print(json.dumps({"fresh_response_sets": fresh}), flush=True)
+            return
         return run(args, spec, wl, stream)
+
+
+def run_nup(args, spec, wl, stream):
+    """Non-uniform partitions (short head, long tail) against uniform ones at
+    the same latency (hop 64, 2L = 128 samples): one call per 64 samples, each
+    pass captured as a HIP graph (a whole number of the non-uniform handle's
+    ring period), HIP events on the stream."""
+    import torch
+
+    from paper_2310_00319_amd import Convolver
+    from paper_2310_00319_amd.nup import NupConvolver
+
+    L, C, K = wl.hop, wl.n_channels, wl.n_slots
+    r, M1 = 8, 7
+    x = torch.from_numpy(wl.padded_input()).cuda()
+    sched = torch.from_numpy(np.ascontiguousarray(wl.schedule, dtype=np.int32)).cuda()
+    out = torch.zeros((C, wl.n_calls * L), device="cuda")
+    nup = NupConvolver(hop=L, tail_ratio=r, head_partitions=M1, n_channels=C, max_taps=wl.max_taps(),
+                       n_inputs=wl.n_inputs, input_of_channel=wl.input_of_channel, n_slots=K, stream=stream)
+    for c in range(C):
+        for k in range(K):
+            nup.set_ir(c, k, wl.taps[c][k])
+    nup.autotune(iters=10)
+    P = nup.period
+    n = (wl.n_calls // P) * P
+
+    def timed(conv, fn):
+        conv.capture_begin()
+        fn()
+        conv.capture_end()
+        conv.graph_launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            conv.graph_launch()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    t0 = time.perf_counter()
+    ms_nup = timed(nup, lambda: nup.process(x, sched, out, n_calls=n))
+    elapsed = time.perf_counter() - t0
+    nup.reset()
+    nup.process(x, sched, out, n_calls=n)
+    torch.cuda.synchronize()
+    got = out[:, : n * L].double().cpu().numpy()
+    nup.close()
+    uni = Convolver(hop=L, n_channels=C, max_taps=wl.max_taps(), n_inputs=wl.n_inputs,
+                    input_of_channel=wl.input_of_channel, n_slots=K, stream=stream)
+    for c in range(C):
+        for k in range(K):
+            uni.set_ir(c, k, wl.taps[c][k])
+    uni.autotune(iters=10)
+    info = uni.info()
+    uni.reset()
+    ms_uni = timed(uni, lambda: uni.process(x[:, : n * L], sched, out[:, : n * L], batch=1))
+    uni.close()
+    us_nup = 1e3 * ms_nup / n
+    us_uni = 1e3 * ms_uni / n
+    accuracy = None
+    if not args.no_cpu_baseline:
+        from oracle import nup_ref
+        xs = wl.padded_input().astype(np.float64)
+        errs = []
+        for c in (0, C - 1):
+            ref = nup_ref.nup_stream(xs[wl.input_of_channel[c]], [t.astype(np.float64) for t in wl.taps[c]],
+                                     wl.schedule[:, c], L, M1, r, int(wl.taps_of_channel[c]), n)
+            errs.append(float(np.linalg.norm(got[c] - ref) / np.linalg.norm(ref)))
+        accuracy = {"vs": "FP64 non-uniform oracle", "channels": [0, C - 1], "max_rel_rms": float(f"{max(errs):.3e}")}
+    res = {
+        "metric": "channel-samples/s at a 128-sample latency, 2-s IRs: non-uniform partitions",
+        "value": round(C * L / (us_nup * 1e-6), 1), "unit": "channel-samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": round(1e3 * elapsed / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"nup: {spec['desc']}", "channels": C, "hop": L, "tail_hop": r * L,
+                   "head_partitions": M1, "ir_taps": int(wl.max_taps()), "calls_per_step": n},
+        "us_per_call": round(us_nup, 3), "latency_samples": 2 * L,
+        "real_time_factor": round((L / wl.fs) / (us_nup * 1e-6), 1),
+        "uniform_same_latency": {"value": round(C * L / (us_uni * 1e-6), 1), "us_per_call": round(us_uni, 3),
+                                 "partitions_per_channel": int(info["sum_partitions"] // C),
+                                 "mac_bytes_per_block": int(info["mac_bytes_per_block"])},
+        "speedup_vs_uniform": round(us_uni / us_nup, 3),
+        "roofline": None, "cpu_baseline": None, "accuracy": accuracy,
+    }
+    print(json.dumps(res), flush=True)
 
 
 def run_autograd(args, spec, wl):
@@ -475,20 +824,16 @@ def run(args, spec, wl, stream):
         if info["fused"] != 1:
             timing = None
 
-    realtime = None
+    streaming = None
     if args.batch > 1 and not args.no_realtime:
-        # strict streaming: one block per call, same workload
-        conv.process(x, sched, out, batch=1)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for k in range(max(1, args.steps // 2)):
-            conv.process(x, sched, out, batch=1)
-        torch.cuda.synchronize()
-        rt_ms = 1e3 * (time.perf_counter() - t1) / max(1, args.steps // 2)
-        realtime = {"value": round(wl.n_channels * wl.n_calls * wl.hop / (rt_ms / 1e3), 1),
-                    "unit": "channel-samples/s", "ms_per_step": round(rt_ms, 4),
-                    "us_per_block": round(1e3 * rt_ms / wl.n_calls, 3),
-                    "real_time_factor": round((wl.hop / wl.fs) / (1e-3 * rt_ms / wl.n_calls), 1)}
+        streaming = streaming_leg(conv, wl, x, sched, out, max(2, args.steps // 2), f"{args.workload} stream k_block")
+        log(f"strict streaming: {streaming['us_per_block']} us per block, "
+            f"{streaming['roofline']['frac']} of HBM peak")
+
+    fresh = None
+    if args.workload == "binaural" and not args.no_fresh:
+        fresh = fresh_legs(args, wl, torch.cuda.current_stream())
+        log(f"fresh response sets: {json.dumps(fresh)}")
 
     ms_per_step = 1e3 * elapsed / args.steps
     blocks = wl.n_calls
@@ -574,7 +919,7 @@ def run(args, spec, wl, stream):
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         ref = []
-        cpu = cpu_baseline(wl, args.cpu_budget, ref)
+        cpu = cpu_baseline(wl, args.workload, args.cpu_budget, ref)
         # accuracy of the same configuration: one fresh pass (untimed) from a
         # reset state, compared per channel with the oracle channels above
         conv.reset()
@@ -619,7 +964,8 @@ def run(args, spec, wl, stream):
         "ir_bank_ingest": ingest,
         "graph": bool(args.graph),
         "blocks_per_call": args.batch,
-        "realtime_one_block_per_call": realtime,
+        "streaming_one_block_per_call": streaming,
+        "fresh_response_sets": fresh,
         "schedule": {"mode": {1: "fused", 2: "two", 0: "plain"}[info["fused"]], "chunk": info["mac_chunk"],
                      "waves": info["mac_waves"], "grid": info["mac_grid"], "work_items": info["n_work_items"],
                      "autotuned_us_per_block": tuned_us,

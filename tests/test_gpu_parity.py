@@ -642,3 +642,71 @@ def test_full_uneven_bench_configuration_matrix_cores():
     err = rel_rms_per_channel(got, oracle_streams(wl, chans))
     log(f"uneven bench configuration (matrix cores): max rel-RMS {err.max():.3e}")
     assert err.max() <= TOL_F32
+
+
+# ------------------------------------------------------------------ head tracking with fresh response sets
+
+def _fresh_small():
+    """A reduced head-tracking case: 3 sources x 2 ears, hop 128, 2500-tap
+    responses, 64 sets per ear and block l using set l mod 64 (every block a
+    new set; none recurs within 64 blocks)."""
+    base = synth.random_small(seed=71, hop=128, n_channels=6, n_inputs=3, n_samples=128 * 150 + 3,
+                              taps_range=(2500, 2500), n_slots=1, p_switch=0.0)
+    base.input_of_channel[:] = np.arange(6) // 2
+    K = 64
+    taps = [[synth.fast_decaying_ir(2500, synth.rng(71, 1, c, k), 48000, 0.3) for k in range(K)] for c in range(6)]
+    import dataclasses
+    sched = np.repeat((np.arange(base.n_calls) % K).astype(np.int32)[:, None], 6, axis=1)
+    return dataclasses.replace(base, taps=taps, n_slots=K, schedule=sched)
+
+
+@pytest.mark.parametrize("batch", [1, 64])
+def test_fresh_set_every_block(batch):
+    """No response set recurs within a call: one block per call and 64-block
+    calls (every time group has as many sets as blocks) against the oracle."""
+    log(f"fresh sets, batch {batch}")
+    wl = _fresh_small()
+    conv = make_convolver(wl, max_batch=64)
+    if batch > 1:
+        conv.autotune_batch(iters=1)
+    got = gpu_streams(wl, conv=conv, batch=batch)
+    conv.close()
+    ref = oracle_streams(wl)
+    err = rel_rms_per_channel(got, ref)
+    elem = max_abs_err_per_channel(got, ref)
+    log(f"fresh sets batch {batch}: rel-RMS {err.max():.3e}, element {elem.max():.3e}")
+    assert err.max() <= TOL_F32 and elem.max() <= ELEM_TOL_F32
+
+
+def test_taps_loaded_every_block_inside_a_graph():
+    """Head tracking with responses arriving as taps: every call first loads
+    the next set of every channel into a slot (tvolap_set_irs from device
+    taps), then processes its block on that slot; the whole stream is one
+    captured graph, replayed, and matches the oracle with one set per block."""
+    import torch
+    log("set_irs before every block, captured")
+    wl = _fresh_small()
+    L, C, K = wl.hop, wl.n_channels, wl.n_slots
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        from paper_2310_00319_amd import Convolver
+        conv = Convolver(hop=L, n_channels=C, max_taps=wl.max_taps(), n_inputs=wl.n_inputs,
+                         input_of_channel=wl.input_of_channel, n_slots=2, stream=stream)
+        pool = torch.from_numpy(np.stack([np.stack([wl.taps[c][k] for c in range(C)]) for k in range(K)])).cuda()
+        x = torch.from_numpy(wl.padded_input()).cuda()
+        slots = torch.from_numpy(np.repeat((np.arange(wl.n_calls) % 2).astype(np.int32)[:, None], C, axis=1)).cuda()
+        out = torch.zeros((C, wl.n_calls * L), device="cuda")
+        stream.synchronize()
+        conv.capture_begin()
+        for c in range(wl.n_calls):
+            conv.set_irs(c % 2, pool[c % K])                   # the set of this block into the other slot
+            conv.process_block(x[:, c * L:(c + 1) * L], out[:, c * L:(c + 1) * L], slots[c])
+        conv.capture_end()
+        conv.graph_launch()
+        stream.synchronize()
+        got = out.cpu().numpy().astype(np.float64)
+        conv.close()
+    ref = oracle_streams(wl)
+    err = rel_rms_per_channel(got, ref)
+    log(f"in-stream loads: rel-RMS {err.max():.3e}")
+    assert err.max() <= TOL_F32 and max_abs_err_per_channel(got, ref).max() <= ELEM_TOL_F32
