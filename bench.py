@@ -86,21 +86,29 @@ def kernel_sources_sha256() -> str:
 def measured_traffic(case: str):
     """HBM bytes per launch from a committed rocprofv3 PMC summary of this case
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when no summary covers
-    the case or the kernel sources changed since the counters were taken."""
+    the case or the kernel sources changed since the counters were taken. A
+    summary may hold several cases, each starting at its traffic_case line."""
     import glob
     want = kernel_sources_sha256()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
-        kv = {}
+        blocks, kv = [], None
         with open(path) as fh:
             for line in fh:
-                if ":" in line and not line.startswith((" ", "|", "#")):
-                    k, v = line.split(":", 1)
-                    kv[k.split(" (")[0].strip()] = v.strip()
-        if kv.get("traffic_case") == case and kv.get("kernel_sources_sha256") == want:
-            try:
-                return int(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
-            except (KeyError, ValueError):
-                return None
+                if ":" not in line or line.startswith((" ", "|", "#")):
+                    continue
+                k, v = line.split(":", 1)
+                k = k.split(" (")[0].strip()
+                if k == "traffic_case":
+                    kv = {}
+                    blocks.append(kv)
+                if kv is not None:
+                    kv[k] = v.strip()
+        for kv in blocks:
+            if kv.get("traffic_case") == case and kv.get("kernel_sources_sha256") == want:
+                try:
+                    return int(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+                except (KeyError, ValueError):
+                    return None
     return None
 
 
@@ -283,6 +291,14 @@ def practical_hbm_rates(mib: int = 1024, reps: int = 10) -> dict:
 USE_GRAPHS = True   # bench.py --no-graph: issue every call directly (hardware-counter passes)
 
 
+def pinned_block(args) -> dict | None:
+    """The one-block schedule given on the command line (--no-autotune with
+    --chunk/--waves/--grid), or None for the autotuner."""
+    if not args.no_autotune:
+        return None
+    return dict(fused=1, chunk=args.chunk, waves=args.waves, grid=args.grid)
+
+
 def graph_step_ms(conv, step_fn, steps: int, warmup: int = 1) -> float:
     """Capture step_fn() once as a HIP graph on the convolver's stream, replay
     it warmup + steps times and return the milliseconds per replay, from events
@@ -328,10 +344,15 @@ def block_roofline(info: dict, us_per_launch: float, case: str) -> dict:
                                "(launch gaps included)"}
 
 
-def streaming_leg(conv, wl, x, sched, out, steps: int, case: str) -> dict:
+def streaming_leg(conv, wl, x, sched, out, steps: int, case: str, pinned: dict | None = None) -> dict:
     """Strict streaming: one process_block per block (latency 2L), per-block
-    schedule autotuned, the calls of one pass captured as a HIP graph."""
-    tuned = conv.autotune(iters=10)
+    schedule autotuned (or `pinned`: configure() arguments), the calls of one
+    pass captured as a HIP graph."""
+    if pinned:
+        conv.configure(**pinned)
+        tuned = None
+    else:
+        tuned = conv.autotune(iters=10)
     info = conv.info()
     conv.reset()
     ms = graph_step_ms(conv, lambda: conv.process(x, sched, out, batch=1), steps)
@@ -380,7 +401,14 @@ def fresh_legs(args, base, stream) -> dict:
     res = {"workload": f"binaural, {K} response sets per ear, block l uses set l mod {K} (no set recurs within "
                        f"{K} blocks)", "ir_sets": K, "bank_bytes": conv.info()["bank_bytes"]}
     # 64-block calls
-    tuned = conv.autotune_batch(iters=2)
+    if args.no_autotune:
+        # the schedule the batched autotuner picks for this workload: vector
+        # ALU, time groups of 8 blocks, 2 bins per lane, one channel per item
+        conv.configure_batch(chunk=args.bchunk, vec=args.bvec or 2, waves=args.bwaves, time_block=args.btb or 8,
+                             group=args.bgroup or 1, engine=1)
+        tuned = None
+    else:
+        tuned = conv.autotune_batch(iters=2)
     info = conv.info()
     conv.reset()
     ms = graph_step_ms(conv, lambda: conv.process(x, sched, out_b, batch=64), steps)
@@ -394,11 +422,13 @@ def fresh_legs(args, base, stream) -> dict:
     kbytes = tmac_unique_bytes(wl, 64, 8) / calls
     gbs = kbytes / (mac_us * 1e-6) / 1e9
     mfma = info["batch_engine"] == 2
+    tr = measured_traffic("binaural_fresh batch64 " + ("k_tmfma" if mfma else "k_tmac"))
     res["blocks_per_call_64"] = {
         "value": round(C * wl.n_calls * L / (ms * 1e-3), 1), "unit": "channel-samples/s",
         "us_per_block": round(1e3 * ms / wl.n_calls, 3), "buffering_ms": round(1e3 * 64 * L / wl.fs, 1),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": tr[0] if tr else None,
+                     "traffic_source": tr[1] if tr else None,
                      "kernel": "batched spectral MAC of eq. 8 (" + ("matrix-core engine with its vector-ALU units" if mfma
                                                                     else "k_tmac, vector ALU") + ")",
                      "bytes_per_launch": int(kbytes), "avg_launch_us": round(mac_us, 3),
@@ -409,10 +439,12 @@ def fresh_legs(args, base, stream) -> dict:
                                "out": round(1e3 * tm["ms_out"] / tm["blocks"], 3)},
         "schedule": {"engine": {1: "vector ALU", 2: "matrix cores"}[info["batch_engine"]],
                      "time_block": info["batch_time_block"], "chunk": info["batch_chunk"],
+                     "vec": info["batch_vec"], "waves": info["batch_waves"], "group": info["batch_group"],
                      "autotuned_us_per_block": tuned}}
     # one block per call
     conv.reset()
-    res["one_block_per_call"] = streaming_leg(conv, wl, x, sched, out_s, steps, "binaural_fresh stream k_block")
+    res["one_block_per_call"] = streaming_leg(conv, wl, x, sched, out_s, steps, "binaural_fresh stream k_block",
+                                              pinned_block(args))
     # one block per call, each preceded by loading the next block's set from taps
     conv.reset()
 
@@ -498,6 +530,8 @@ def main():
     ap.add_argument("--bengine", type=int, default=0,
                     help="batched MAC engine: 1 = vector ALU, 2 = matrix cores (f32 spectra)")
     ap.add_argument("--no-ingest", action="store_true", help="skip the IR-bank ingestion timing")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the forward/backward timing of the "
+                                                                  "differentiable form")
     ap.add_argument("--fresh-only", action="store_true",
                     help="only the legs with 64 response sets per ear (binaural)")
     ap.add_argument("--no-fresh", action="store_true",
@@ -636,9 +670,9 @@ def run_nup(args, spec, wl, stream):
     print(json.dumps(res), flush=True)
 
 
-def run_autograd(args, spec, wl):
+def autograd_times(wl, steps: int, warmup: int) -> dict:
     """Offline differentiable form: MSE loss against the hidden-IR target,
-    forward and backward (gradients for H and x) timed separately."""
+    forward and backward (gradients for H and x) timed separately with events."""
     import torch
 
     from paper_2310_00319_amd import functional as F
@@ -652,13 +686,13 @@ def run_autograd(args, spec, wl):
     def fwd():
         return torch.mean((F.tvolap(x, H, L) - target) ** 2)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         fwd().backward()
     torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     f_ms = b_ms = 0.0
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         x.grad = None
         H.grad = None
         e[0].record()
@@ -670,19 +704,27 @@ def run_autograd(args, spec, wl):
         f_ms += e[0].elapsed_time(e[1])
         b_ms += e[1].elapsed_time(e[2])
     elapsed = time.perf_counter() - t0
-    f_ms /= args.steps
-    b_ms /= args.steps
-    ms_per_step = 1e3 * elapsed / args.steps
+    return {"forward_ms": round(f_ms / steps, 4), "backward_ms": round(b_ms / steps, 4),
+            "backward_forward_ratio": round(b_ms / f_ms, 3), "ms_per_step": round(1e3 * elapsed / steps, 4),
+            "channels": C, "hop": L, "partitions": int(H.shape[2]), "samples": N,
+            "partitions_note": "input spectra recomputed in the backward pass, not stored"}
+
+
+def run_autograd(args, spec, wl):
+    """Offline differentiable form: MSE loss against the hidden-IR target,
+    forward and backward (gradients for H and x) timed separately."""
+    C, N, L = wl.n_channels, wl.n_samples, wl.hop
+    t = autograd_times(wl, args.steps, args.warmup)
     res = {
         "metric": "channel-samples/s of one forward + backward pass (offline differentiable TVOLAP)",
-        "value": round(C * N / (ms_per_step / 1e3), 1),
+        "value": round(C * N / (t["ms_per_step"] / 1e3), 1),
         "unit": "channel-samples/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"autograd: {spec['desc']}", "channels": C, "hop": L, "ir_taps": int(wl.max_taps()),
-                   "partitions": int(H.shape[2]), "samples": N},
-        "forward_ms": round(f_ms, 4), "backward_ms": round(b_ms, 4),
-        "backward_forward_ratio": round(b_ms / f_ms, 3),
+                   "partitions": t["partitions"], "samples": N},
+        "forward_ms": t["forward_ms"], "backward_ms": t["backward_ms"],
+        "backward_forward_ratio": t["backward_forward_ratio"],
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(res), flush=True)
@@ -826,9 +868,17 @@ def run(args, spec, wl, stream):
 
     streaming = None
     if args.batch > 1 and not args.no_realtime:
-        streaming = streaming_leg(conv, wl, x, sched, out, max(2, args.steps // 2), f"{args.workload} stream k_block")
+        streaming = streaming_leg(conv, wl, x, sched, out, max(2, args.steps // 2), f"{args.workload} stream k_block",
+                                  pinned_block(args))
         log(f"strict streaming: {streaming['us_per_block']} us per block, "
             f"{streaming['roofline']['frac']} of HBM peak")
+
+    autograd = None
+    if args.workload == "binaural" and not args.no_autograd:
+        import synth
+        autograd = autograd_times(synth.autograd(), max(3, args.steps // 2), 1)
+        autograd["workload"] = WORKLOADS["autograd"]["desc"]
+        log(f"autograd: {autograd}")
 
     fresh = None
     if args.workload == "binaural" and not args.no_fresh:
@@ -966,6 +1016,7 @@ def run(args, spec, wl, stream):
         "blocks_per_call": args.batch,
         "streaming_one_block_per_call": streaming,
         "fresh_response_sets": fresh,
+        "autograd_forward_backward": autograd,
         "schedule": {"mode": {1: "fused", 2: "two", 0: "plain"}[info["fused"]], "chunk": info["mac_chunk"],
                      "waves": info["mac_waves"], "grid": info["mac_grid"], "work_items": info["n_work_items"],
                      "autotuned_us_per_block": tuned_us,

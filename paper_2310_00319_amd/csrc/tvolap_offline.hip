@@ -43,8 +43,9 @@ struct Shape {
   int64_t N;
 };
 
-// Twiddles exp(-2 pi i t / 4L) and the window (1 - cos(2 pi n / 2L)) / 2,
-// evaluated in double precision and rounded to float, into LDS.
+// Twiddles exp(-2 pi i t / 4L), evaluated in double precision and rounded to
+// float, into LDS; the window (1 - cos(2 pi n / 2L)) / 2 = (1 - Re tw(2n)) / 2
+// from them in float. Called by every thread of the workgroup.
 template <int L>
 __device__ __forceinline__ void make_tables(float2* twl, float* winl, int tid) {
   for (int t = tid; t < 4 * L; t += T) {
@@ -52,8 +53,10 @@ __device__ __forceinline__ void make_tables(float2* twl, float* winl, int tid) {
     sincospi(-(double)t / (double)(2 * L), &sn, &cs);
     twl[t] = make_float2((float)cs, (float)sn);
   }
-  if (winl)
-    for (int n = tid; n < 2 * L; n += T) winl[n] = (float)(0.5 * (1.0 - cospi((double)n / (double)L)));
+  if (winl) {
+    __syncthreads();
+    for (int n = tid; n < 2 * L; n += T) winl[n] = 0.5f * (1.0f - twl[2 * n].x);
+  }
 }
 
 // packed product; bin 0 carries two real bins and multiplies component-wise
