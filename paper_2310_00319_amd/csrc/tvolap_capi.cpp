@@ -325,6 +325,7 @@ void build_work(tvolap_t* h, int S_req, int waves, int vec) {
         w.m1 = std::min(s.M, 1 + (j + 1) * S);
         w.tile = t;
         w.chunk = j;
+        w.nch = nch;
         for (int g = 0; g < 4; ++g) {
           const int c = g < w.n_ch ? s.ch[g] : s.ch[0];
           w.ch[g] = c;
@@ -457,6 +458,7 @@ void build_batch_work(tvolap_t* h, const BatchChoice& bc) {
         w.m1 = std::min(sb.M, (j + 1) * S);
         w.tile = t;
         w.chunk = j;
+        w.nch = nch;
         for (int g = 0; g < 4; ++g) {
           const int c = g < w.n_ch ? sb.ch[g] : sb.ch[0];
           w.ch[g] = c;

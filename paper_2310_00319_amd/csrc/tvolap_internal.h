@@ -37,10 +37,11 @@ struct DevPlan {
 // over the partitions [max(m0, 1), m1) (chunk `chunk` of the channels'
 // partition range; the m = 0 term is added when the channel is completed).
 // Channel g writes its partial spectrum tile to row[g] of the partial buffer;
-// the rows of a channel are contiguous, ordered (tile, chunk).
+// the rows of a channel are contiguous, ordered (tile, chunk), nch chunks per
+// tile (the same for all channels of an item).
 struct WorkItem {
   int32_t input, n_ch, m0, m1;
-  int32_t tile, chunk, kind, pad;
+  int32_t tile, chunk, kind, nch;
   int32_t ch[4];
   int32_t row[4];
 };

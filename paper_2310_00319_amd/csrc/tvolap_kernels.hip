@@ -187,6 +187,29 @@ __device__ __forceinline__ void load_tables(const DevPlan& P, float2* twl, float
 // the parity's ring of M_i spectra.
 __device__ __forceinline__ int ring_slot(uint64_t cnt, int Mi) { return (int)((cnt >> 1) % (uint64_t)Mi); }
 
+// Where the completion of a channel reads (stored-element offsets): X(l), its
+// input's spectrum of this block, in the delay line; H_{c, slot}(0) in the
+// bank; its first partial row and the partial rows per tile.
+struct FinDesc {
+  int64_t x, h;
+  int32_t rows, nch;
+};
+template <int L>
+__device__ __forceinline__ FinDesc lookup_desc(const DevPlan& P, const int32_t* __restrict__ sel, int c, int p,
+                                               uint64_t cnt) {
+  constexpr int N = 2 * L;
+  const int i = P.ch_input[c];
+  const int Mi = P.in_M[i];
+  int s = sel[c];
+  s = s < 0 ? 0 : (s >= P.K ? P.K - 1 : s);
+  FinDesc d;
+  d.x = P.in_fdl_off[i] + ((int64_t)p * Mi + ring_slot(cnt, Mi)) * N;
+  d.h = P.ch_bank_off[c] + (int64_t)s * P.ch_M[c] * N;
+  d.rows = P.ch_row_base[c];
+  d.nch = P.ch_nchunks[c];
+  return d;
+}
+
 // New input spectrum of input i (eq. 1, 2, 4, 5): the 2L-sample block (the
 // previous L samples, history parity p^1, then the L new ones) weighted by the
 // window, zero padded to 4L and transformed; the packed spectrum, rounded to
@@ -223,12 +246,14 @@ __device__ __forceinline__ void input_spectrum(const DevPlan& P, const float* __
 // acc[g] += H_{c_g, slot}(m) X(l - 2m) for this lane's V bins. The waves of the
 // workgroup take every NW-th partition; two partitions are in flight per wave.
 // The packed bin 0 holds two real bins and multiplies component-wise.
+// fd (LDS, may be null): thread 0 also records there the completion
+// descriptors of the item's channels, from the offsets the MAC computes anyway.
 template <int V, int G, int NW, int DT, int U>
 __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
                                          const typename Store<DT>::T* __restrict__ bank,
                                          const typename Store<DT>::T* __restrict__ fdl,
                                          const int32_t* __restrict__ sel, int p, uint64_t cnt, int lane, int w,
-                                         float2 (&acc)[G][V]) {
+                                         float2 (&acc)[G][V], FinDesc* fd = nullptr) {
   using ST = typename Store<DT>::T;
   constexpr int TW = 64 * V;
   const int N = 2 * P.L;
@@ -250,6 +275,19 @@ __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
     } else {
       Mc[g] = 0;
       hbase[g] = bank;
+    }
+  }
+  if (fd != nullptr && lane == 0 && w == 0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (g < it.n_ch) {
+        FinDesc d;
+        d.x = (xbase - fdl) + (int64_t)q * N;
+        d.h = hbase[g] - bank;
+        d.rows = it.row[g] - it.tile * it.nch - it.chunk;
+        d.nch = it.nch;
+        fd[g] = d;
+      }
     }
   }
   const bool dc_lane = (kbase == 0);
@@ -414,19 +452,81 @@ __device__ __forceinline__ void channel_spectrum(const DevPlan& P, const float2*
   }
 }
 
-// Complete channel c: spectrum, inverse transform and overlap-add.
+// Spectra of NC (1 or 2) channels into Y[0 .. NC) (LDS), as channel_spectrum
+// computes each (the same sums in the same order), from their completion
+// descriptors. The delay-line, bank and first partial-row loads of all the
+// channels are issued before any of them is used, so the completion waits
+// for memory once. COHERENT as in channel_spectrum. No barrier at the end.
+template <int L, int T, int DT, bool COHERENT, int NC>
+__device__ __forceinline__ void desc_spectra(const float2* __restrict__ ypart, int TW,
+                                             const typename Store<DT>::T* __restrict__ bank,
+                                             const typename Store<DT>::T* __restrict__ fdl, const FinDesc* d,
+                                             float2* const (&Y)[NC], int tid) {
+  using ST = typename Store<DT>::T;
+  constexpr int N = 2 * L;
+  const ST* xrow[NC];
+  const ST* h0[NC];
+  const float2* rows[NC];
+  int nch[NC];
+#pragma unroll
+  for (int g = 0; g < NC; ++g) {
+    xrow[g] = fdl + d[g].x;
+    h0[g] = bank + d[g].h;
+    rows[g] = ypart + (int64_t)d[g].rows * TW;
+    nch[g] = d[g].nch;
+  }
+#pragma unroll
+  for (int k = tid; k < N; k += T) {
+    const int t = k / TW;
+    const int b = k - t * TW;
+    float2 X[NC], H[NC], a0[NC];
+    const float2* src[NC];
+#pragma unroll
+    for (int g = 0; g < NC; ++g) {
+      X[g] = unpack<DT>(load_maybe<COHERENT>(xrow[g] + k));
+      H[g] = unpack<DT>(h0[g][k]);
+      src[g] = rows[g] + (int64_t)t * nch[g] * TW + b;
+      a0[g] = nch[g] > 0 ? load_maybe<COHERENT>(src[g]) : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int g = 0; g < NC; ++g) {
+      float2 s0 = (k == 0) ? make_float2(H[g].x * X[g].x, H[g].y * X[g].y) : cmul(H[g], X[g]);
+      float2 s1 = make_float2(0.f, 0.f), s2 = s1, s3 = s1;
+      const int n = nch[g];
+      int j = 0;
+      if (n >= 4) {
+        s0 = cadd(s0, a0[g]);
+        s1 = cadd(s1, load_maybe<COHERENT>(src[g] + (int64_t)1 * TW));
+        s2 = cadd(s2, load_maybe<COHERENT>(src[g] + (int64_t)2 * TW));
+        s3 = cadd(s3, load_maybe<COHERENT>(src[g] + (int64_t)3 * TW));
+        for (j = 4; j + 4 <= n; j += 4) {
+          const float2 b0 = load_maybe<COHERENT>(src[g] + (int64_t)(j + 0) * TW);
+          const float2 b1 = load_maybe<COHERENT>(src[g] + (int64_t)(j + 1) * TW);
+          const float2 b2 = load_maybe<COHERENT>(src[g] + (int64_t)(j + 2) * TW);
+          const float2 b3 = load_maybe<COHERENT>(src[g] + (int64_t)(j + 3) * TW);
+          s0 = cadd(s0, b0); s1 = cadd(s1, b1); s2 = cadd(s2, b2); s3 = cadd(s3, b3);
+        }
+      }
+      for (; j < n; ++j) s0 = cadd(s0, j == 0 ? a0[g] : load_maybe<COHERENT>(src[g] + (int64_t)j * TW));
+      Y[g][k] = cadd(cadd(s0, s1), cadd(s2, s3));
+    }
+  }
+}
+
+// Complete channel c (completion descriptor d): spectrum, inverse transform
+// and overlap-add.
 template <int L, int T, int DT, bool COHERENT>
-__device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __restrict__ ypart,
+__device__ __forceinline__ void channel_final(const float2* __restrict__ ypart, int TW,
                                               const typename Store<DT>::T* __restrict__ bank,
-                                              const typename Store<DT>::T* __restrict__ fdl,
-                                              const int32_t* __restrict__ sel, int c, int p, uint64_t cnt,
+                                              const typename Store<DT>::T* __restrict__ fdl, const FinDesc* d, int c,
                                               float2* Y, float2* bufA, float2* bufB, const float2* twl,
                                               float* __restrict__ ola, float* __restrict__ out, int64_t out_stride,
                                               int tid) {
   float* st = ola + (int64_t)c * 3 * L;
   float old[(4 * L + T - 1) / T];
   ola_prefetch<L, T>(st, old, tid);    // in flight together with the spectrum's loads
-  channel_spectrum<L, T, DT, COHERENT>(P, ypart, bank, fdl, sel, c, p, cnt, Y, tid);
+  float2* const Ys[1] = {Y};
+  desc_spectra<L, T, DT, COHERENT, 1>(ypart, TW, bank, fdl, d, Ys, tid);
   __syncthreads();
   inverse_ola<L, T>(Y, bufA, bufB, twl, old, st, out + (int64_t)c * out_stride, tid);
 }
@@ -435,12 +535,12 @@ __device__ __forceinline__ void channel_final(const DevPlan& P, const float2* __
 // inverse transform of Y0 + i Y1 (both outputs are real, so the real part is
 // channel c0's block and the imaginary part channel c1's), overlap-add of both.
 // Ya, Yb: 2L each; F0, F1: 4L each (LDS). twl holds exp(-2 pi i t / 4L).
+// d: the completion descriptors of c0 and c1.
 template <int L, int T, int DT, bool COHERENT>
-__device__ __forceinline__ void pair_final(const DevPlan& P, const float2* __restrict__ ypart,
+__device__ __forceinline__ void pair_final(const float2* __restrict__ ypart, int TW,
                                            const typename Store<DT>::T* __restrict__ bank,
-                                           const typename Store<DT>::T* __restrict__ fdl,
-                                           const int32_t* __restrict__ sel, int c0, int c1, int p, uint64_t cnt,
-                                           float2* Ya, float2* Yb, float2* F0, float2* F1, const float2* twl,
+                                           const typename Store<DT>::T* __restrict__ fdl, const FinDesc* d, int c0,
+                                           int c1, float2* Ya, float2* Yb, float2* F0, float2* F1, const float2* twl,
                                            float* __restrict__ ola, float* __restrict__ out, int64_t out_stride,
                                            int tid) {
   constexpr int N = 2 * L;
@@ -450,8 +550,8 @@ __device__ __forceinline__ void pair_final(const DevPlan& P, const float2* __res
   float old0[NPT], old1[NPT];
   ola_prefetch<L, T>(st0, old0, tid);
   ola_prefetch<L, T>(st1, old1, tid);
-  channel_spectrum<L, T, DT, COHERENT>(P, ypart, bank, fdl, sel, c0, p, cnt, Ya, tid);
-  channel_spectrum<L, T, DT, COHERENT>(P, ypart, bank, fdl, sel, c1, p, cnt, Yb, tid);
+  float2* const Ys[2] = {Ya, Yb};
+  desc_spectra<L, T, DT, COHERENT, 2>(ypart, TW, bank, fdl, d, Ys, tid);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
@@ -542,6 +642,7 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
   __shared__ float2 ybuf[N];
   __shared__ float2 pool[POOL];
   __shared__ int cand[4];
+  __shared__ FinDesc fin[4];   // completion descriptors of cand
   __shared__ int won[4];
   __shared__ int nwon;
   auto red = reinterpret_cast<float2 (*)[G][TW]>(pool);
@@ -558,9 +659,9 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
   // neither spectrum items nor channel completions wait for them later.
   load_tables<L, T>(P, twl, winl, tid);
 
-  // Count one arrival for the channel group cand[0 .. n) (set by thread 0;
-  // the channels go through LDS so that the work item stays in registers) and,
-  // if last, the item itself. A group (the channels of an input that share
+  // Count one arrival for the channel group cand[0 .. n) (channels and their
+  // completion descriptors fin[0 .. n) set by the caller; they go through LDS
+  // so that the work item stays in registers) and, if last, the item itself. A group (the channels of an input that share
   // work items) has one counter, kept under its first channel: every item
   // publishes all the group's data before it counts, so the arrival that
   // completes the counter completes every channel of the group, and the
@@ -569,13 +670,21 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
   auto arrive = [&](int n, bool last_of_item) {
     if (tid == 0) {
       const int c0 = cand[0];
+      // The group's quota and both counters are in flight together (one
+      // round trip). Increments rather than additions: the compiler issues
+      // them as written, without the wave-level aggregation it builds around
+      // an addition, whose wait would put the second counter behind the first.
+      const int need = A.needed[c0];
+      const int a = (int)atomicInc(reinterpret_cast<unsigned int*>(&A.arrive[c0]), 0xffffffffu);
+      const int d = last_of_item ? (int)atomicInc(reinterpret_cast<unsigned int*>(A.done), 0xffffffffu) : -1;
       int k = 0;
-      if (atomicAdd(&A.arrive[c0], 1) == A.needed[c0] - 1) {
+      if (a == need - 1) {
         for (int j = 0; j < n; ++j) won[j] = cand[j];
         k = n;
       }
+      // (won[j] keeps fin[j]: the winner completes cand in order)
       nwon = k;
-      if (last_of_item && atomicAdd(A.done, 1) == A.n_items - 1) {
+      if (d == A.n_items - 1) {
         // every item has started, so every workgroup has read the call count
         *A.done = 0;
         *A.counter = cnt + 1u;
@@ -585,10 +694,10 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
     const int k = nwon;
     for (int j = 0; j < k; j += 2) {
       if (j + 1 < k)
-        pair_final<L, T, DT, true>(P, A.ypart, bank, fdl, A.sel, won[j], won[j + 1], p, cnt, bufA, bufB, pool,
+        pair_final<L, T, DT, true>(A.ypart, TW, bank, fdl, fin + j, won[j], won[j + 1], bufA, bufB, pool,
                                    pool + 2 * N, twl, A.ola, A.out, A.out_stride, tid);
       else
-        channel_final<L, T, DT, true>(P, A.ypart, bank, fdl, A.sel, won[j], p, cnt, ybuf, bufA, bufB, twl, A.ola,
+        channel_final<L, T, DT, true>(A.ypart, TW, bank, fdl, fin + j, won[j], ybuf, bufA, bufB, twl, A.ola,
                                       A.out, A.out_stride, tid);
       __syncthreads();
     }
@@ -612,8 +721,12 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
         const int j1 = P.in_ch_ptr[it.input + 1];
         for (int j = P.in_ch_ptr[it.input]; j < j1; j += G) {
           const int n = min(G, j1 - j);
-          if (tid == 0)
-            for (int q = 0; q < n; ++q) cand[q] = P.in_ch[j + q];
+          if (tid < n) {
+            const int c = P.in_ch[j + tid];
+            cand[tid] = c;
+            fin[tid] = lookup_desc<L>(P, A.sel, c, p, cnt);
+          }
+          __syncthreads();
           arrive(n, j + G >= j1);
         }
       } else {
@@ -626,7 +739,7 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
       float2 acc[G][V];
       // two partitions in flight per wave keep the streaming loop well within
       // the register budget
-      mac_item<V, G, NW, DT, 2>(P, it, bank, fdl, A.sel, p, cnt, lane, w, acc);
+      mac_item<V, G, NW, DT, 2>(P, it, bank, fdl, A.sel, p, cnt, lane, w, acc, inl ? fin : nullptr);
       if (inl) {
         write_partials<V, G, NW, true>(it, acc, red, A.ypart, lane, w, tid);
         wait_memory();
