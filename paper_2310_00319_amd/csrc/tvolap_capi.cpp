@@ -132,7 +132,6 @@ struct tvolap {
   int32_t* d_bnchunks = nullptr;
   float2* d_bypart = nullptr;     // [max_batch][n_brows][b_tile_width]
   int32_t* d_defer = nullptr;     // [1 + units]: count, then units the matrix-core MAC defers
-  float* d_yblk = nullptr;        // [max_batch][C][4L]
   int32_t* d_tune_bsel = nullptr; // [max_batch][C] autotuner schedule (slot = block mod K)
 
   // pinned staging ring for host slot selections
@@ -234,7 +233,7 @@ void free_all(tvolap_t* h) {
   dfree(h->d_counter); dfree(h->d_tw); dfree(h->d_win); dfree(h->d_ch_input); dfree(h->d_ch_M);
   dfree(h->d_ch_bank_off); dfree(h->d_in_M); dfree(h->d_in_fdl_off); dfree(h->d_taps);
   dfree(h->d_arrive); dfree(h->d_done); dfree(h->d_zero_in); dfree(h->d_tune_out); dfree(h->d_tune_sel);
-  dfree(h->d_in_ch_ptr); dfree(h->d_in_ch); dfree(h->d_part_base); dfree(h->d_ch_taps); dfree(h->d_yblk); dfree(h->d_tune_bsel);
+  dfree(h->d_in_ch_ptr); dfree(h->d_in_ch); dfree(h->d_part_base); dfree(h->d_ch_taps); dfree(h->d_tune_bsel);
   if (h->events_made)
     for (auto& t : h->tsets)
       for (auto& e : t.ev) (void)hipEventDestroy(e);
@@ -630,7 +629,6 @@ int create_impl(const tvolap_config* cfg, tvolap_t* h) {
   HIP_TRY(h, dalloc(&h->d_zero_in, (size_t)h->I * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_tune_out, (size_t)h->C * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_tune_sel, (size_t)h->K * h->C * sizeof(int32_t)));
-  HIP_TRY(h, dalloc(&h->d_yblk, (size_t)h->max_batch * h->C * 4 * L * sizeof(float)));
   HIP_TRY(h, dalloc(&h->d_tune_bsel, (size_t)h->max_batch * h->C * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_in_ch_ptr, (size_t)(h->I + 1) * sizeof(int32_t)));
   HIP_TRY(h, dalloc(&h->d_in_ch, (size_t)h->C * sizeof(int32_t)));
@@ -992,9 +990,7 @@ int enqueue_blocks(tvolap_t* h, const float* in, int64_t in_stride, int32_t n_bl
   B.sel_store = h->d_sel;
   B.copy_sel = (slots_dev && copy_sel) ? 1 : 0;
   B.ypart = h->d_bypart;
-  B.yblk = h->d_yblk;
   B.ola_state = h->d_ola;
-  B.arrive = h->d_arrive;
   B.done = h->d_done;
   B.counter = h->d_counter;
   B.bus_rows = h->mixdown ? 1 : 0;

@@ -107,10 +107,8 @@ struct BatchArgs {
   int32_t* sel_store;
   int32_t copy_sel;
   float2* ypart;               // [n_max][rows][tile_width]
-  float* yblk;                 // [n_max][C][4L]
   float* ola_state;            // [C][3L]
-  int32_t* arrive;             // [C] overlap-add workgroups finished per output (zero between calls)
-  int32_t* done;
+  int32_t* done;               // [1] workgroups of the batch's last launch finished
   uint64_t* counter;
   int32_t bus_rows;            // 1: mixdown; bus sums are formed in the partial rows before the inverse
   // Work units (time groups of an item) that the matrix-core MAC leaves to

@@ -599,24 +599,6 @@ __device__ __forceinline__ void pair_final(const float2* __restrict__ ypart, int
   }
 }
 
-// Inverse real DFT of the packed spectrum Y (eq. 9): the 4L samples of the
-// block's output go to dst (16-byte aligned), four per store.
-template <int L, int T>
-__device__ __forceinline__ void inverse_store(float2* Y, float2* bufA, float2* bufB, const float2* twl,
-                                              float* __restrict__ dst, int tid) {
-  constexpr int N = 2 * L;
-#pragma unroll
-  for (int k = tid; k < N; k += T) bufA[k] = fft::real_inv_pre_conj<N>(Y, k, twl);
-  __syncthreads();
-  const float2* R = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
-  constexpr float scale = 1.0f / (float)(4 * L);
-#pragma unroll
-  for (int n4 = tid; n4 < L; n4 += T) {
-    const float2 z0 = R[2 * n4], z1 = R[2 * n4 + 1];
-    reinterpret_cast<float4*>(dst)[n4] = make_float4(z0.x * scale, -z0.y * scale, z1.x * scale, -z1.y * scale);
-  }
-}
-
 // ---------------------------------------------------------------- fused per-block kernel
 
 // Work items: kind 1 = new spectrum of one input (placed first), kind 0 = MAC
@@ -761,10 +743,11 @@ __global__ __launch_bounds__(64 * NW) void k_block(BlockArgs A) {
 // ---------------------------------------------------------------- batched blocks
 
 // Batches of n consecutive blocks (calls cnt .. cnt+n-1) in three launches:
-// all input spectra, one MAC launch whose last item per (block, channel)
-// transforms back into a block buffer, and a per-channel overlap-add in call
-// order. The delay line holds M_i + (n_max-1)/2 spectra per parity, so a
-// batch's new spectra never replace ones that its own blocks still read.
+// all input spectra, one MAC launch that writes partial spectrum rows per
+// (block, channel), and one launch that transforms back and overlap-adds the
+// outputs' windows. The delay line holds M_i + (n_max-1)/2 spectra per
+// parity, so a batch's new spectra never replace ones that its own blocks
+// still read.
 
 // Blocks per workgroup in the batched transform kernels (their twiddle and
 // window tables are loaded once per workgroup).
@@ -1737,7 +1720,7 @@ __global__ __launch_bounds__(64 * NWV) void k_tmfma16(BatchArgs B) {
 // Mixdown of a batch: for block j, bus e and 64 bins, the sum over the bus's
 // channels and their partition chunks of the partial rows (the channels'
 // spectra Y, eq. 8, are added before one inverse transform per bus), written
-// over the first channel's chunk-0 row, which k_batch_inv then reads alone.
+// over the first channel's chunk-0 row, which k_batch_out then reads alone.
 // Four slices of the channel list are summed apart (four channels' loads in
 // flight per thread) and added in a fixed order.
 template <int L>
@@ -1792,160 +1775,180 @@ __device__ __forceinline__ float4 add4(float4 a, float4 b) {
   return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
 }
 
-// Block j, channel c of a batch: the sum of the channel's partial rows (all
-// partitions, eq. 8) and the inverse transform (eq. 9) into the block buffer.
-template <int L>
-__global__ __launch_bounds__(256) void k_batch_inv(BatchArgs B, int bpw) {
-  constexpr int N = 2 * L;
-  constexpr int T = 256;
-  __shared__ float2 twl[2 * N];
-  __shared__ float winl[N];
-  __shared__ float2 Y[N];
-  __shared__ float2 bufA[N];
-  __shared__ float2 bufB[N];
-  const DevPlan& P = B.P;
-  const int e = blockIdx.x, tid = threadIdx.x;    // output bus
-  load_tables<L, T>(P, twl, winl, tid);
-  const int TW = B.tile_width;
-  const int c0 = P.out_ptr[e];
-  // with bus sums in place (B.bus_rows), the first channel's chunk-0 rows hold the bus
-  const int c1 = B.bus_rows ? c0 + 1 : P.out_ptr[e + 1];
-  // bpw consecutive blocks per workgroup (tables loaded once)
-  for (int u = 0; u < bpw; ++u) {
-    const int j = blockIdx.y * bpw + u;
-    if (j >= B.n_blocks) break;
-    const float2* yp = B.ypart + (int64_t)j * B.n_rows * TW;
-    // two bins per thread (tile widths are even: both lie in one tile row)
-    for (int k = 2 * tid; k < N; k += 2 * T) {
-      const int t = k / TW;
-      const int kk = k - t * TW;
-      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-      for (int qc = c0; qc < c1; ++qc) {
-        const int c = P.out_ch[qc];
-        const int nrow = B.nchunks[c];
-        const int nch = B.bus_rows ? 1 : nrow;
-        const float4* src = reinterpret_cast<const float4*>(yp + ((int64_t)B.row_base[c] + (int64_t)t * nrow) * TW + kk);
-        const int64_t rs = TW / 2;   // row stride in float4
-        float4 s0 = src[0];
-        float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        int q = 1;
-        for (; q + 1 < nch; q += 2) {
-          s0 = add4(s0, src[(int64_t)q * rs]);
-          s1 = add4(s1, src[(int64_t)(q + 1) * rs]);
-        }
-        if (q < nch) s0 = add4(s0, src[(int64_t)q * rs]);
-        acc = (qc == c0) ? add4(s0, s1) : add4(acc, add4(s0, s1));
-      }
-      Y[k] = make_float2(acc.x, acc.y);
-      Y[k + 1] = make_float2(acc.z, acc.w);
-    }
-    __syncthreads();
-    inverse_store<L, T>(Y, bufA, bufB, twl, B.yblk + ((int64_t)j * P.n_out + e) * 4 * L, tid);
-    __syncthreads();
-  }
+// v * i^m (m = 0..3): a quarter-turn rotation of a complex value.
+__device__ __forceinline__ float2 rot_i(float2 v, int m) {
+  const float a = (m & 1) ? v.y : v.x;
+  const float b = (m & 1) ? v.x : v.y;
+  return make_float2(((m + 1) & 2) ? -a : a, (m & 2) ? -b : b);
 }
 
-// Overlap-add of the batch's n blocks (eq. 10-13 in the two-step form), grid
-// (max(C, I), S): workgroup (c, s) emits a range of 4 x 256 samples of
-// channel c. Emitted window j of the batch (samples jL .. jL+L) is the carried
-// state for j < 3 plus the quarter d of block j - d for d = 0..3, summed
-// oldest block first (the order of one-block calls); every block sample is
-// read once. The carried state (3L samples) is replaced by the last workgroup
-// of the channel to finish: every workgroup reads the old state it needs
-// before it arrives, so nothing waits and the old state is never overwritten
-// early. Workgroups with s = 0 also store the input history (rows c < I) and
-// the selection; the last workgroup of the grid advances the call count by n.
-// Output samples per thread of the batched overlap-add (two 4-sample loads
-// per row in flight per thread).
-constexpr int kOlaSamplesPerThread = 8;
+// Windows per workgroup of the batched output (at most).
+constexpr int kOutWindows = 8;
 
+// Fused inverse transform and overlap-add of a batch (eq. 9-13), grid
+// (max(n_out, I), G): workgroup (e, g) owns output bus e and the windows
+// [gW, min(n, gW + W)) of the batch, window w being the samples wL .. wL + L
+// of the call's output. A circular shift by dL samples of a 4L-sample block is
+// the factor i^{kd} on bin k of its spectrum, so the sum that the overlap-add
+// forms for window w, quarter d of block w - d over d = 0..3, is the first
+// quarter of one inverse transform of Z_w(k) = sum_d i^{kd} Y_{w-d}(k). The
+// workgroup loads its blocks at once (three before its first window, W <=
+// kOutWindows windows), forms the windows' Z four at a time and transforms
+// them side by side, one wave per window. Windows 0..2 add the state carried
+// from the previous call. Workgroups (e, 0) also form the new carried state
+// (windows n .. n+2, from blocks n-3 .. n-1 and the old state where n + q < 3)
+// after they have read the old one, so no workgroup waits for another;
+// workgroups (x, 0) store the input history and the selection, and the last
+// of them advances the call count by n.
 template <int L>
-__global__ __launch_bounds__(256) void k_batch_ola(BatchArgs B, const float* __restrict__ in, int64_t in_stride,
-                                                   float* __restrict__ hist, float* __restrict__ ola,
-                                                   float* __restrict__ out, int64_t out_stride) {
+__global__ __launch_bounds__(256) void k_batch_out(BatchArgs B, int W, const float* __restrict__ in,
+                                                   int64_t in_stride, float* __restrict__ hist,
+                                                   float* __restrict__ ola, float* __restrict__ out,
+                                                   int64_t out_stride) {
   constexpr int T = 256;
-  constexpr int R = 4;                     // samples per load
-  constexpr int V = kOlaSamplesPerThread / R;   // loads per thread and row
-  constexpr int SPW = kOlaSamplesPerThread * T;  // samples per workgroup
+  constexpr int NWV = T / 64;              // windows transformed side by side
+  constexpr int N = 2 * L;                 // packed bins; the inverse is an N-point complex FFT
+  constexpr int BP = (L + T - 1) / T;      // bin pairs per thread
+  constexpr int NB = kOutWindows + 6;      // block slots of one pass (window w uses slot w - b0 + 3)
+  __shared__ float2 twl[2 * N];
+  __shared__ float2 Zs[NWV][N];            // window sums, then the transforms' second buffer
+  __shared__ float2 Fs[NWV][N];            // the transforms' first buffer
+  __shared__ float sto[3 * L];             // carried state of the previous call
   const DevPlan& P = B.P;
-  const int c = blockIdx.x, sw = blockIdx.y, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int e = blockIdx.x, g = blockIdx.y;
   const int n = B.n_blocks;
-  // only the workgroups of the first sample range read the call count (for
-  // the history parity); they alone count towards advancing it
-  const uint64_t cnt0 = (sw == 0) ? *B.counter : 0;
-  __shared__ int last;
-  if (c < P.n_out) {                       // output bus c
-    float* st = ola + (int64_t)c * 3 * L;
-    const float* yc = B.yblk + (int64_t)c * 4 * L;     // block j at yc + j * n_out * 4L
-    const int64_t ystride = (int64_t)P.n_out * 4 * L;
-    float* oc = out + (int64_t)c * out_stride;
-    // V groups of R consecutive samples per thread, each within one window
-    // (L is a multiple of R): block and state rows are read R at a time
-    static_assert(L % R == 0, "whole sample groups per window");
+  const uint64_t cnt0 = (g == 0) ? *B.counter : 0;
+  if (e < P.n_out) {
+    for (int i = tid; i < 2 * N; i += T) twl[i] = P.tw[i];
+    float* st = ola + (int64_t)e * 3 * L;
+    if (g == 0)
+      for (int i = tid; i < 3 * L; i += T) sto[i] = st[i];
+    const int TW = B.tile_width;
+    // the bus's spectrum rows: its first channel's rows (with a mixdown, that
+    // channel's chunk-0 rows hold the bus sum), nsum rows per tile
+    const int c = P.out_ch[P.out_ptr[e]];
+    const int nrow = B.nchunks[c];
+    const int nsum = B.bus_rows ? 1 : nrow;
+    const float4* src[BP];
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-    const int t = sw * SPW + R * (v * T + tid);
-    if (t < n * L) {
-      const int j = t / L, k = t - j * L;
-      float4 a = (j < 3) ? *reinterpret_cast<const float4*>(st + j * L + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int r = 0; r < BP; ++r) {
+      const int k = 2 * (tid + T * r);
+      const int t = k / TW;
+      src[r] = reinterpret_cast<const float4*>(B.ypart + ((int64_t)B.row_base[c] + (int64_t)t * nrow) * TW +
+                                               (k - t * TW));
+    }
+    const int64_t bstride = (int64_t)B.n_rows * TW / 2;   // float4 per block
+    const int rstride = TW / 2;                           // float4 per row
+    auto load_y = [&](int b, float4 (&y)[BP]) {
 #pragma unroll
-      for (int d = 3; d >= 0; --d)
-        if (j - d >= 0) a = add4(a, *reinterpret_cast<const float4*>(yc + (int64_t)(j - d) * ystride + d * L + k));
-      if ((reinterpret_cast<uintptr_t>(oc + t) & 15) == 0) {
-        *reinterpret_cast<float4*>(oc + t) = a;
-      } else {
-        oc[t] = a.x;
-        oc[t + 1] = a.y;
-        oc[t + 2] = a.z;
-        oc[t + 3] = a.w;
+      for (int r = 0; r < BP; ++r) {
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (2 * (tid + T * r) < N) {
+          const float4* s = src[r] + (int64_t)b * bstride;
+          a = s[0];
+          for (int q = 1; q < nsum; ++q) a = add4(a, s[(int64_t)q * rstride]);
+        }
+        y[r] = a;
       }
-    }
-    }
-    // every read of the old state above has returned (its value is stored)
-    __syncthreads();
-    if (tid == 0) last = (atomicAdd(&B.arrive[c], 1) == (int)gridDim.y - 1) ? 1 : 0;
-    __syncthreads();
-    if (last) {
-      // new carried state u = qL + k: windows n + q, q < 3; all of it is read
-      // before any of it is written
-      constexpr int NS = (3 * L + T - 1) / T;
-      float ns[NS];
+    };
+    constexpr float scale = 1.0f / (float)(4 * L);
+    __syncthreads();   // twiddles and old state; the old state is read before any new one is stored
+
+    // One or two passes: the windows [w0, w1) from the blocks [b0, b1), all
+    // of whose spectra are loaded first (at most W + 3 of them: every load of
+    // the pass is in flight at once), block b into slot b - w0 + 3, so that
+    // window w = w0 + v - 3 sums the slots v - 3 .. v (slots of blocks outside
+    // [b0, b1) hold zeros: before the batch, the carried state stands for
+    // them). The first window group also forms the windows n .. n+2 of the
+    // new carried state: in its own pass over the last three blocks when it
+    // does not reach them.
+    const int j0 = g * W, j1 = min(n, j0 + W);
+    const int npass = (g == 0 && j1 < n) ? 2 : 1;
+    for (int ps = 0; ps < npass; ++ps) {
+      int w0, w1, b0, b1;
+      if (g != 0) {
+        w0 = j0; w1 = j1; b0 = j0 - 3; b1 = j1;
+      } else if (ps == 0) {
+        w0 = 0; w1 = (j1 == n) ? n + 3 : j1; b0 = 0; b1 = j1;
+      } else {
+        w0 = n; w1 = n + 3; b0 = n - 3; b1 = n;
+      }
+      float4 y[NB][BP];
 #pragma unroll
-      for (int e = 0; e < NS; ++e) {
-        const int u = tid + e * T;
-        ns[e] = 0.f;
-        if (u < 3 * L) {
-          const int q = u / L, k = u - q * L;
-          float a = (n + q < 3) ? st[(n + q) * L + k] : 0.f;
+      for (int u = 0; u < NB; ++u) {
+        const int b = w0 - 3 + u;
+        if (b >= b0 && b < b1) {
+          load_y(b, y[u]);
+        } else {
 #pragma unroll
-          for (int d = 3; d >= 1; --d) {
-            const int j = n + q - d;
-            if (d > q && j >= 0) a += yc[(int64_t)j * ystride + d * L + k];
-          }
-          ns[e] = a;
+          for (int r = 0; r < BP; ++r) y[u][r] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
       }
-      __syncthreads();
+      // windows w = w0 + v - 3, v from 3, NWV at a time
 #pragma unroll
-      for (int e = 0; e < NS; ++e) {
-        const int u = tid + e * T;
-        if (u < 3 * L) st[u] = ns[e];
+      for (int v0 = 3; v0 < NB; v0 += NWV) {
+        if (w0 + v0 - 3 < w1) {
+          // Z_w = sum over d of i^{kd} Y_{w-d}, oldest block first, into Zs
+#pragma unroll
+          for (int h = 0; h < NWV; ++h) {
+            const int v = v0 + h;
+            if (v < NB) {
+#pragma unroll
+              for (int r = 0; r < BP; ++r) {
+                const int k = 2 * (tid + T * r);
+                float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int d = 3; d >= 0; --d) {
+                  if (v - d >= 0) {   // slots outside [b0, b1) hold zeros
+                    const float4 yy = y[v >= d ? v - d : 0][r];
+                    // k = 0: slot 0 holds the real bins 0 and 2L, whose
+                    // factors are 1 (L is even)
+                    const float2 lo = rot_i(make_float2(yy.x, yy.y), (k * d) & 3);
+                    const float2 hi = rot_i(make_float2(yy.z, yy.w), ((k + 1) * d) & 3);
+                    z = add4(z, make_float4(lo.x, lo.y, hi.x, hi.y));
+                  }
+                }
+                if (k < N) reinterpret_cast<float4*>(Zs[h])[k >> 1] = z;
+              }
+            }
+          }
+          __syncthreads();
+          // wave wv transforms window w0 + v0 - 3 + wv (every wave runs the
+          // transform; one outside [w0, w1) discards its result)
+          float2* Z = Zs[wv];
+          float2* F = Fs[wv];
+          for (int k = lane; k < N; k += 64) F[k] = fft::real_inv_pre_conj<N>(Z, k, twl);
+          __syncthreads();
+          const float2* R = fft::fft_fwd<N, 64>(F, Z, twl, lane);
+          const int w = w0 + v0 - 3 + wv;
+          if (w >= w0 && w < w1) {
+            for (int t = lane; t < L; t += 64) {
+              const float2 zz = R[t >> 1];
+              float val = ((t & 1) ? -zz.y : zz.x) * scale;
+              if (w < 3) val += sto[w * L + t];
+              if (w < n) out[(int64_t)e * out_stride + (int64_t)w * L + t] = val;
+              else st[(w - n) * L + t] = val;   // new carried state
+            }
+          }
+          __syncthreads();   // Zs and Fs are reused by the next windows
+        }
       }
-      if (tid == 0) B.arrive[c] = 0;
-      // slots of the bus's channels at the batch's last block, one channel per thread
-      if (B.copy_sel)
-        for (int q = P.out_ptr[c] + tid; q < P.out_ptr[c + 1]; q += T)
-          B.sel_store[P.out_ch[q]] = B.sel[(int64_t)(n - 1) * B.sel_stride + P.out_ch[q]];
     }
+    // slots of the bus's channels at the batch's last block
+    if (g == 0 && B.copy_sel)
+      for (int q = P.out_ptr[e] + tid; q < P.out_ptr[e + 1]; q += T)
+        B.sel_store[P.out_ch[q]] = B.sel[(int64_t)(n - 1) * B.sel_stride + P.out_ch[q]];
   }
-  if (c < P.I && sw == 0) {
+  if (e < P.I && g == 0) {
     const uint64_t lastc = cnt0 + (uint64_t)(n - 1);
-    float* hnew = hist + ((size_t)(lastc & 1u) * P.I + c) * L;
-    const float* xin = in + (int64_t)c * in_stride + (int64_t)(n - 1) * L;
+    float* hnew = hist + ((size_t)(lastc & 1u) * P.I + e) * L;
+    const float* xin = in + (int64_t)e * in_stride + (int64_t)(n - 1) * L;
     for (int k = tid; k < L; k += T) hnew[k] = xin[k];
   }
   __syncthreads();
-  if (tid == 0 && sw == 0) {
+  if (tid == 0 && g == 0) {
     if (atomicAdd(B.done, 1) == (int)gridDim.x - 1) {
       *B.done = 0;
       *B.counter = cnt0 + (uint64_t)n;
@@ -2357,15 +2360,16 @@ hipError_t hop_batch(const BatchArgs& B, int dtype, const MacShape& shape, int g
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    // few outputs: one block per workgroup, for more workgroups
-    const int bpw = (B.P.n_out * bgroups < 256) ? 1 : kBatchBlocksPerWg;
-    hipLaunchKernelGGL((k_batch_inv<L>), dim3(B.P.n_out, (B.n_blocks + bpw - 1) / bpw), dim3(256), 0, s, B, bpw);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int wgs = B.P.n_out > B.P.I ? B.P.n_out : B.P.I;
-    const int spw = (B.n_blocks * L + kOlaSamplesPerThread * 256 - 1) / (kOlaSamplesPerThread * 256);
-    hipLaunchKernelGGL((k_batch_ola<L>), dim3(wgs, spw), dim3(256), 0, s, B, in, in_stride, hist, B.ola_state, out,
-                       out_stride);
+    // windows per workgroup: enough workgroups for four per compute unit, at
+    // least four windows each (a group also reads the three blocks before its
+    // first), at most kOutWindows
+    const int no = B.P.n_out;
+    const int want = (B.n_blocks * no + 1023) / 1024;
+    const int W = std::min(kOutWindows, std::max(4, want));
+    const int groups = (B.n_blocks + W - 1) / W;
+    const int gx = no > B.P.I ? no : B.P.I;
+    hipLaunchKernelGGL((k_batch_out<L>), dim3(gx, groups), dim3(256), 0, s, B, W, in, in_stride, hist, B.ola_state,
+                       out, out_stride);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev) e = hipEventRecord(ev[3], s);
