@@ -302,7 +302,11 @@ typedef struct {
   int64_t n_samples;      /* N >= 1                                         */
 } tvolap_offline_shape;
 
-/* Workspace size in bytes, or -1 for an invalid shape. */
+/* Workspace size in bytes, or -1 for an invalid shape. Both calls run the
+ * signal in segments of up to 1024 hops, so the workspace grows with the
+ * segment and not with N: the packed partition spectra (C K M 2L complex
+ * values) plus, per channel, the spectra of 1024 + 2M + 2 blocks twice and
+ * 1028 blocks of 4L samples (less for signals shorter than a segment). */
 int64_t tvolap_offline_workspace_bytes(const tvolap_offline_shape* shape);
 
 /* H[c][s][m][k] (k = 0 .. 2L) of taps[c][s][0 .. n_taps): partition m holds
@@ -319,7 +323,9 @@ int tvolap_offline_forward(const tvolap_offline_shape* shape, const float* x, co
 /* Adjoint of the forward map for a real loss with gradient gy = dLoss/dy
  * ([C][N]): dx[c][t] = dLoss/dx[c][t] and dH[c][s][m][k] = dLoss/dRe H +
  * i dLoss/dIm H (zero imaginary parts at k = 0 and 2L). Either output may be
- * NULL to skip it. The input spectra are recomputed from x. */
+ * NULL to skip it. The input spectra are recomputed from x, segment by
+ * segment, with the 2(M - 1) blocks before each segment recomputed too; dH
+ * is summed over the segments. */
 int tvolap_offline_backward(const tvolap_offline_shape* shape, const float* x, const float* H,
                             const int32_t* schedule, const float* gy, float* dx, float* dH, void* workspace,
                             int64_t workspace_bytes, void* stream);

@@ -810,14 +810,31 @@ __global__ __launch_bounds__(256) void k_batch_spectra(DevPlan P, const float* _
 
 // Slot pattern of an item's blocks, per channel: one slot for all blocks,
 // two slots alternating with the block index, two slots in any order (each
-// block picks its slot's spectrum with a select), or any assignment of up to
-// two slots per pass (blocks of further slots take further passes).
-enum TmacPattern { kOneSlot = 1, kAlternating = 2, kSelect = 3, kTwoSlots = 4 };
+// block picks its slot's spectrum with a select), any assignment of up to two
+// slots per pass (blocks of further slots take further passes), or every
+// block its own slot's spectrum in one pass (the delay-line window is read
+// once however many slots the blocks use; for one-channel items small enough
+// to hold a partition row per block in registers).
+enum TmacPattern { kOneSlot = 1, kAlternating = 2, kSelect = 3, kTwoSlots = 4, kPerBlock = 5 };
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Number of distinct values among n uniform slots.
+template <int n>
+__device__ __forceinline__ int distinct_slots(const int (&sl)[n]) {
+  int d = 0;
+#pragma unroll
+  for (int b = 0; b < n; ++b) {
+    bool seen = false;
+#pragma unroll
+    for (int a = 0; a < b; ++a) seen = seen || (sl[a] == sl[b]);
+    d += seen ? 0 : 1;
+  }
+  return d;
+}
 
 // f(integral_constant<int, i>) for i = 0 .. n-1, unrolled at compile time.
 template <typename F, int... Is>
@@ -925,11 +942,14 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
     // next rows, loaded ahead of use.
     const bool dcw = (it.tile == 0 && w == 0);   // this wave holds the packed DC / Nyquist bin
     const bool dc_lane = dcw && lane == 0;
-    auto run = [&](auto patc, auto dcwc, const ST* const (&hr)[G][2], const uint32_t (&sel1)[G],
-                   const uint32_t (&take)[G]) {
+    // hr[g][d]: partition rows of slot set d of channel g (d < 2; for
+    // kPerBlock d = block, d < TB)
+    auto run = [&](auto patc, auto dcwc, const auto& hr, const uint32_t (&sel1)[G], const uint32_t (&take)[G]) {
       constexpr int PAT = decltype(patc)::value;
       constexpr bool DCW = decltype(dcwc)::value;
-      constexpr int ND = (PAT == kOneSlot) ? 1 : 2;
+      constexpr int ND = (PAT == kOneSlot) ? 1 : (PAT == kPerBlock ? TB : 2);
+      // partitions loaded ahead (a row per block in flight for kPerBlock)
+      constexpr int PDP = (PAT == kPerBlock) ? 2 : PD;
       // f32 storage: values as float2, four FMAs per complex product. 16-bit
       // storage: raw words (Re in the low half, Im in the high half) and two
       // packed dot products with FP32 accumulation per complex product:
@@ -968,8 +988,8 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
 #pragma unroll
         for (int v = 0; v < V; ++v) X[b][v] = entry(w[v], v);
       }
-      HW Hq[PD][G][ND][V];
-      HW Xq[PD][V];
+      HW Hq[PDP][G][ND][V];
+      HW Xq[PDP][V];
       auto load_h = [&](HW (&Hs)[G][ND][V], int mm) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -1035,6 +1055,7 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
                   bool use;
                   if constexpr (PAT == kOneSlot) use = true;
                   else if constexpr (PAT == kAlternating) use = ((b & 1) == d);
+                  else if constexpr (PAT == kPerBlock) use = (b == d);
                   else use = true;
                   if (use) {
                     const XW& x = X[(b - T0 + TB) % TB][v];
@@ -1076,7 +1097,7 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
         }
       };
 #pragma unroll
-      for (int st = 0; st < PD; ++st) {
+      for (int st = 0; st < PDP; ++st) {
         load_h(Hq[st], m0 + st);
         load_x(Xq[st], m0 + st + 1);
       }
@@ -1085,11 +1106,11 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
       // block TB - 1's row of partition mm was
       auto advance = [&](int mm, auto tc) {
         constexpr int t = decltype(tc)::value;
-        step(Hq[t % PD], mm, tc);
-        load_h(Hq[t % PD], mm + PD);
+        step(Hq[t % PDP], mm, tc);
+        load_h(Hq[t % PDP], mm + PDP);
 #pragma unroll
-        for (int v = 0; v < V; ++v) X[(TB - 1 - t) % TB][v] = entry(Xq[t % PD][v], v);
-        load_x(Xq[t % PD], mm + 1 + PD);
+        for (int v = 0; v < V; ++v) X[(TB - 1 - t) % TB][v] = entry(Xq[t % PDP][v], v);
+        load_x(Xq[t % PDP], mm + 1 + PDP);
       };
       int mb = m0;
       for (; mb + TB <= m1; mb += TB) static_for<TB>([&](auto tc) { advance(mb + decltype(tc)::value, tc); });
@@ -1132,6 +1153,24 @@ __global__ __launch_bounds__(256) void k_tmac(BatchArgs B) {
       }
       if (dcw) run(std::integral_constant<int, kTwoSlots>{}, std::true_type{}, hr, sel1, none);
       else run(std::integral_constant<int, kTwoSlots>{}, std::false_type{}, hr, sel1, none);
+    } else if (G == 1 && TB * V <= 16 && 2 * distinct_slots(slot[0]) > TB) {
+      // more distinct slots than half the blocks: every block its own row,
+      // one pass (a pass per two slots would read the delay-line window
+      // more than TB / 4 times; with fewer slots the passes issue fewer
+      // loads). One-channel items only: the row registers would cost the
+      // two-channel forms occupancy on every pattern.
+      const ST* hr[G][TB];
+      uint32_t none[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        none[g] = 0u;
+#pragma unroll
+        for (int b = 0; b < TB; ++b) hr[g][b] = hch[g] + (int64_t)slot[g][b] * McL[g] * N;
+      }
+      if constexpr (G == 1 && TB * V <= 16) {
+        if (dcw) run(std::integral_constant<int, kPerBlock>{}, std::true_type{}, hr, none, none);
+        else run(std::integral_constant<int, kPerBlock>{}, std::false_type{}, hr, none, none);
+      }
     } else {
       // passes of up to two slots per channel
       uint32_t todo[G];

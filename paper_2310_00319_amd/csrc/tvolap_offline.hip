@@ -171,14 +171,16 @@ __global__ __launch_bounds__(T) void k_ola(Shape S, const float* __restrict__ yb
   }
 }
 
-// G_b = (c_k / 4L) DFT_4L(gy over [(b-1)L, (b+3)L)) -> gspec[c][b][2L] (packed)
+// G_b = (c_k / 4L) DFT_4L(gy over [(b-1)L, (b+3)L)) for b = gb0 .. gb0 + gn - 1
+// -> gspec[c][b - gb0][2L] (packed)
 template <int L>
-__global__ __launch_bounds__(T) void k_gspec(Shape S, const float* __restrict__ gy, float2* __restrict__ gspec) {
+__global__ __launch_bounds__(T) void k_gspec(Shape S, const float* __restrict__ gy, float2* __restrict__ gspec,
+                                             int32_t gb0, int32_t gn) {
   constexpr int N = 2 * L;
   __shared__ float2 twl[2 * N];
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
-  const int b = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const int b = gb0 + (int)blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
   make_tables<L>(twl, nullptr, tid);
   const float* g = gy + (int64_t)c * S.N;
   const int64_t t0 = (int64_t)(b - 1) * L;
@@ -190,57 +192,66 @@ __global__ __launch_bounds__(T) void k_gspec(Shape S, const float* __restrict__ 
   const float2* Z = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
   constexpr float end = 1.0f / (float)(4 * L);
   constexpr float mid = 2.0f / (float)(4 * L);
-  float2* dst = gspec + ((int64_t)c * S.nblk + b) * N;
+  float2* dst = gspec + ((int64_t)c * gn + blockIdx.x) * N;
   for (int k = tid; k < N; k += T) dst[k] = cscale(fft::real_fwd_post<N>(Z, k, twl), k == 0 ? end : mid);
 }
 
-// dH[c][s][m][k] = sum_{b: g(b)=s, b-2m >= 0} G_b(k) conj(X_{b-2m}(k)), written unpacked ([2L+1] bins)
-__global__ __launch_bounds__(T) void k_dH(Shape S, const float2* __restrict__ gspec, const float2* __restrict__ Xall,
-                                          const int32_t* __restrict__ sched, float2* __restrict__ dH) {
+// dH[c][s][m][k] (+)= sum over blocks b in [b0, b1) with g(b) = s and b - 2m >= 0
+// of G_b(k) conj(X_{b-2m}(k)), written unpacked ([2L+1] bins); G_b at
+// gspec[c][b - gb0], X_b at Xbuf[c][b - xb0]. acc = 0: the first segment
+// writes, later ones add.
+__global__ __launch_bounds__(T) void k_dH(Shape S, const float2* __restrict__ gspec, int32_t gb0, int32_t gn,
+                                          const float2* __restrict__ Xbuf, int32_t xb0, int32_t xn,
+                                          const int32_t* __restrict__ sched, int32_t b0, int32_t b1, int32_t acc_in,
+                                          float2* __restrict__ dH) {
   const int N = 2 * S.L;
   const int64_t row = blockIdx.x;                    // (c, s, m)
   const int m = (int)(row % S.M);
   const int s = (int)((row / S.M) % S.K);
   const int c = (int)(row / ((int64_t)S.M * S.K));
-  const float2* G = gspec + (int64_t)c * S.nblk * N;
-  const float2* X = Xall + (int64_t)c * S.nblk * N;
+  const float2* G = gspec + (int64_t)c * gn * N;
+  const float2* X = Xbuf + (int64_t)c * xn * N;
   float2* dst = dH + row * (N + 1);
   for (int k = threadIdx.x; k < N; k += T) {
     float2 acc = make_float2(0.f, 0.f);
-    for (int b = 2 * m; b < S.nblk; ++b) {
+    for (int b = max(b0, 2 * m); b < b1; ++b) {
       if (slot_of(sched, b, c, S.C, S.K) != s) continue;
-      acc = cadd(acc, pmulc(G[(int64_t)b * N + k], X[(int64_t)(b - 2 * m) * N + k], k == 0));
+      acc = cadd(acc, pmulc(G[(int64_t)(b - gb0) * N + k], X[(int64_t)(b - 2 * m - xb0) * N + k], k == 0));
     }
     if (k == 0) {
-      dst[0] = make_float2(acc.x, 0.f);
-      dst[N] = make_float2(acc.y, 0.f);
+      float2 d0 = make_float2(acc.x, 0.f), dn = make_float2(acc.y, 0.f);
+      if (acc_in) { d0.x += dst[0].x; dn.x += dst[N].x; }
+      dst[0] = d0;
+      dst[N] = dn;
     } else {
-      dst[k] = acc;
+      dst[k] = acc_in ? cadd(dst[k], acc) : acc;
     }
   }
 }
 
-// dxhat_j = w . (first 2L samples of the R2C adjoint of dX_j) -> dxb[c][j][2L]
+// dxhat_j = w . (first 2L samples of the R2C adjoint of dX_j) for j = j0 ..
+// j0 + jn - 1 -> dxb[c][j - j0][2L]; G_b at gspec[c][b - gb0] for every
+// b = j + 2m < nblk
 template <int L>
-__global__ __launch_bounds__(T) void k_dx_blocks(Shape S, const float2* __restrict__ gspec,
+__global__ __launch_bounds__(T) void k_dx_blocks(Shape S, const float2* __restrict__ gspec, int32_t gb0, int32_t gn,
                                                  const float2* __restrict__ Hp, const int32_t* __restrict__ sched,
-                                                 float* __restrict__ dxb) {
+                                                 float* __restrict__ dxb, int32_t j0, int32_t jn) {
   constexpr int N = 2 * L;
   __shared__ float2 twl[2 * N];
   __shared__ float winl[N];
   __shared__ float2 D[N];
   __shared__ float2 bufA[N];
   __shared__ float2 bufB[N];
-  const int j = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+  const int j = j0 + (int)blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
   make_tables<L>(twl, winl, tid);
-  const float2* G = gspec + (int64_t)c * S.nblk * N;
+  const float2* G = gspec + (int64_t)c * gn * N;
   for (int k = tid; k < N; k += T) {
     float2 acc = make_float2(0.f, 0.f);
     for (int m = 0; m < S.M && j + 2 * m < S.nblk; ++m) {
       const int b = j + 2 * m;
       const int s = slot_of(sched, b, c, S.C, S.K);
       const float2* H = Hp + (((int64_t)c * S.K + s) * S.M + m) * N;
-      acc = cadd(acc, pmulc(G[(int64_t)b * N + k], H[k], k == 0));
+      acc = cadd(acc, pmulc(G[(int64_t)(b - gb0) * N + k], H[k], k == 0));
     }
     // sum_k Re(D(k) e^{+i theta}) over the 2L + 1 bins equals the normalised
     // inverse real DFT of D scaled by 4L at k = 0, 2L and by 2L elsewhere
@@ -251,25 +262,27 @@ __global__ __launch_bounds__(T) void k_dx_blocks(Shape S, const float2* __restri
   __syncthreads();
   const float2* R = fft::fft_fwd<N, T>(bufA, bufB, twl, tid);
   constexpr float scale = 1.0f / (float)(4 * L);
-  float* dst = dxb + ((int64_t)c * S.nblk + j) * N;
+  float* dst = dxb + ((int64_t)c * jn + blockIdx.x) * N;
   for (int n = tid; n < N; n += T) {
     const float2 z = R[n >> 1];
     dst[n] = winl[n] * ((n & 1) ? -z.y : z.x) * scale;
   }
 }
 
-// dx[c][t] = sum of the two windowed blocks that cover t
-__global__ __launch_bounds__(T) void k_dx_ola(Shape S, const float* __restrict__ dxb, float* __restrict__ dx) {
+// dx[c][t] for t in [t0, t1) = sum of the two windowed blocks that cover t
+// (blocks q and q + 1 for t in hop q, both in dxb = blocks j0 .. j0 + jn - 1)
+__global__ __launch_bounds__(T) void k_dx_ola(Shape S, const float* __restrict__ dxb, int32_t j0, int32_t jn,
+                                              int64_t t0, int64_t t1, float* __restrict__ dx) {
   const int c = blockIdx.y;
   const int L = S.L;
   const int N = 2 * L;
-  for (int64_t t = (int64_t)blockIdx.x * T + threadIdx.x; t < S.N; t += (int64_t)gridDim.x * T) {
+  for (int64_t t = t0 + (int64_t)blockIdx.x * T + threadIdx.x; t < t1; t += (int64_t)gridDim.x * T) {
     const int64_t q = t / L;
     float acc = 0.f;
     for (int64_t j = q; j <= q + 1; ++j) {
       if (j < 0 || j >= S.nblk) continue;
       const int64_t off = t - (j - 1) * L;
-      if (off >= 0 && off < N) acc += dxb[((int64_t)c * S.nblk + j) * N + off];
+      if (off >= 0 && off < N) acc += dxb[((int64_t)c * jn + (j - j0)) * N + off];
     }
     dx[(int64_t)c * S.N + t] = acc;
   }
@@ -325,14 +338,23 @@ hipError_t by_hop(int L, F&& f) {
 
 struct Workspace {
   float2* Hp;      // [C][K][M][2L]
-  float2* Xall;    // [C][nblk][2L]
-  float* blk;      // [C][nblk][4L] (forward output blocks / gradient spectra)
+  float2* Xbuf;    // [C][nx][2L] input spectra of one segment
+  float2* Gbuf;    // [C][nx][2L] gradient spectra of one segment
+  float* blk;      // [C][nq + 4][4L] forward output blocks / windowed gradient blocks of one segment
 };
 
 int64_t align_up(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
+// Hops per segment of the workspace forms: the working memory grows with the
+// segment, not with the signal (a segment of nq hops holds the spectra of
+// nq + 4 + 2(M - 1) blocks per channel).
+constexpr int64_t kSegHops = 1024;
+int64_t seg_hops(const Shape& S) { return std::min<int64_t>((int64_t)S.nblk - 1, kSegHops); }
+
 int64_t workspace_layout(const Shape& S, Workspace* w, char* base) {
   const int N = 2 * S.L;
+  const int64_t nq = seg_hops(S);
+  const int64_t nx = nq + 4 + 2 * ((int64_t)S.M - 1);
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
     const int64_t o = off;
@@ -340,11 +362,13 @@ int64_t workspace_layout(const Shape& S, Workspace* w, char* base) {
     return o;
   };
   const int64_t o_hp = take((int64_t)S.C * S.K * S.M * N * 8);
-  const int64_t o_x = take((int64_t)S.C * S.nblk * N * 8);
-  const int64_t o_b = take((int64_t)S.C * S.nblk * 4 * S.L * 4);
+  const int64_t o_x = take((int64_t)S.C * nx * N * 8);
+  const int64_t o_g = take((int64_t)S.C * nx * N * 8);
+  const int64_t o_b = take((int64_t)S.C * (nq + 4) * 4 * S.L * 4);
   if (w && base) {
     w->Hp = reinterpret_cast<float2*>(base + o_hp);
-    w->Xall = reinterpret_cast<float2*>(base + o_x);
+    w->Xbuf = reinterpret_cast<float2*>(base + o_x);
+    w->Gbuf = reinterpret_cast<float2*>(base + o_g);
     w->blk = reinterpret_cast<float*>(base + o_b);
   }
   return off;
@@ -505,8 +529,8 @@ int tvolap_offline_forward(const tvolap_offline_shape* shape, const float* x, co
   hipStream_t st = static_cast<hipStream_t>(stream);
   Workspace w;
   if (int rc = prepare(S, workspace, workspace_bytes, &w)) return rc;
-  const hipError_t e = tvx::off::forward_segments(S, x, reinterpret_cast<const float2*>(H), schedule, y, w.Xall,
-                                                  w.blk, (int64_t)S.nblk - 1, st);
+  const hipError_t e = tvx::off::forward_segments(S, x, reinterpret_cast<const float2*>(H), schedule, y, w.Xbuf,
+                                                  w.blk, tvx::off::seg_hops(S), st);
   if (e != hipSuccess) return off_fail(TVOLAP_EDEVICE, hipGetErrorString(e));
   return TVOLAP_OK;
 }
@@ -520,29 +544,41 @@ int tvolap_offline_backward(const tvolap_offline_shape* shape, const float* x, c
   hipStream_t st = static_cast<hipStream_t>(stream);
   Workspace w;
   if (int rc = prepare(S, workspace, workspace_bytes, &w)) return rc;
-  const dim3 gb(S.nblk, S.C);
   const unsigned rows = (unsigned)((int64_t)S.C * S.K * S.M);
-  const unsigned ola_x = (unsigned)std::min<int64_t>((S.N + tvx::off::T - 1) / tvx::off::T, 65535);
-  // the block buffer (4L floats per block) holds the 2L packed gradient spectra
-  float2* gspec = reinterpret_cast<float2*>(w.blk);
+  const int64_t nq = tvx::off::seg_hops(S);
+  const int64_t M2 = 2 * ((int64_t)S.M - 1);
   const hipError_t e = tvx::off::by_hop(S.L, [&](auto Lc) {
     constexpr int L = decltype(Lc)::value;
     using namespace tvx::off;
     hipLaunchKernelGGL(k_pack, dim3(rows), dim3(T), 0, st, S, reinterpret_cast<const float2*>(H), w.Hp);
-    hipLaunchKernelGGL((k_gspec<L>), gb, dim3(T), 0, st, S, gy, gspec);
-    if (dH) {
-      // delay line recomputed from x
-      hipLaunchKernelGGL((k_spectra<L>), gb, dim3(T), 0, st, S, x, w.Xall, 0, S.nblk);
-      hipLaunchKernelGGL(k_dH, dim3(rows), dim3(T), 0, st, S, gspec, w.Xall, schedule,
-                         reinterpret_cast<float2*>(dH));
+    // Segments of hops [Q0, Q1): dx over their samples (windowed blocks Q0 ..
+    // Q1, each from the gradient spectra of the blocks j + 2m after it), dH
+    // over the blocks [Q0, Q1) (the last segment also takes block nblk - 1),
+    // with the input spectra of 2(M - 1) blocks before them recomputed from x.
+    for (int64_t Q0 = 0; Q0 < (int64_t)S.nblk - 1; Q0 += nq) {
+      const int64_t Q1 = std::min<int64_t>(Q0 + nq, (int64_t)S.nblk - 1);
+      const int64_t hb1 = (Q1 == (int64_t)S.nblk - 1) ? S.nblk : Q1;       // dH blocks [Q0, hb1)
+      const int64_t jb1 = std::min<int64_t>(S.nblk, Q1 + 1);                // dx blocks [Q0, jb1)
+      const int64_t gb1 = std::min<int64_t>(S.nblk, std::max(hb1, jb1 + M2));  // gradient spectra [Q0, gb1)
+      const int64_t xb0 = std::max<int64_t>(0, Q0 - M2);                     // input spectra [xb0, hb1)
+      const int32_t gn = (int32_t)(gb1 - Q0), xn = (int32_t)(hb1 - xb0), jn = (int32_t)(jb1 - Q0);
+      hipLaunchKernelGGL((k_gspec<L>), dim3(gn, S.C), dim3(T), 0, st, S, gy, w.Gbuf, (int32_t)Q0, gn);
+      if (dH) {
+        hipLaunchKernelGGL((k_spectra<L>), dim3(xn, S.C), dim3(T), 0, st, S, x, w.Xbuf, (int32_t)xb0, xn);
+        hipLaunchKernelGGL(k_dH, dim3(rows), dim3(T), 0, st, S, w.Gbuf, (int32_t)Q0, gn, w.Xbuf, (int32_t)xb0, xn,
+                           schedule, (int32_t)Q0, (int32_t)hb1, (int32_t)(Q0 > 0), reinterpret_cast<float2*>(dH));
+      }
+      if (dx) {
+        const int64_t t0 = Q0 * S.L, t1 = std::min<int64_t>(S.N, Q1 * S.L);
+        const unsigned ola_x = (unsigned)std::min<int64_t>((t1 - t0 + T - 1) / T, 65535);
+        hipLaunchKernelGGL((k_dx_blocks<L>), dim3(jn, S.C), dim3(T), 0, st, S, w.Gbuf, (int32_t)Q0, gn, w.Hp,
+                           schedule, w.blk, (int32_t)Q0, jn);
+        hipLaunchKernelGGL(k_dx_ola, dim3(ola_x, S.C), dim3(T), 0, st, S, w.blk, (int32_t)Q0, jn, t0, t1, dx);
+      }
+      const hipError_t le = hipGetLastError();
+      if (le != hipSuccess) return le;
     }
-    if (dx) {
-      // the input spectra are no longer needed: their space holds the windowed blocks
-      float* dxb = reinterpret_cast<float*>(w.Xall);
-      hipLaunchKernelGGL((k_dx_blocks<L>), gb, dim3(T), 0, st, S, gspec, w.Hp, schedule, dxb);
-      hipLaunchKernelGGL(k_dx_ola, dim3(ola_x, S.C), dim3(T), 0, st, S, dxb, dx);
-    }
-    return hipGetLastError();
+    return hipSuccess;
   });
   if (e != hipSuccess) return off_fail(TVOLAP_EDEVICE, hipGetErrorString(e));
   return TVOLAP_OK;

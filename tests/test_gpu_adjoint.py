@@ -54,10 +54,15 @@ CASES = [
     (2, 128, 2, 2, 5, 128 * 15),
     (3, 256, 2, 3, 4, 256 * 9 + 100),
     (4, 512, 1, 2, 2, 512 * 8 + 1),
+    # signals longer than one segment of the workspace forms (1024 hops): the
+    # backward runs in segments, the input spectra of the 2(M - 1) blocks
+    # before each recomputed and dH summed over the segments
+    (5, 64, 2, 2, 4, 64 * 2100 + 33),
+    (6, 128, 1, 3, 40, 128 * 1100),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"L{c[1]}_K{c[3]}" for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"L{c[1]}_K{c[3]}_M{c[4]}_N{c[5]}" for c in CASES])
 def test_offline_forward_and_adjoint_match_oracle(case):
     import torch
     from paper_2310_00319_amd import functional as F

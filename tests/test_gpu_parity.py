@@ -678,6 +678,46 @@ def test_fresh_set_every_block(batch):
     assert err.max() <= TOL_F32 and elem.max() <= ELEM_TOL_F32
 
 
+# vector-ALU schedules with one channel per item, where a time group with more
+# distinct slots than half its blocks takes every block's own partition rows in
+# one pass (and a group with fewer takes passes of two slots)
+PER_BLOCK_CASES = [
+    # (slot period, vec, time_block, batch, dtype)
+    (64, 2, 8, 64, "f32"),     # every block its own set
+    (64, 1, 16, 64, "f32"),
+    (64, 1, 8, 37, "f32"),     # ragged batch
+    (10, 2, 8, 64, "f32"),     # five slots among the 8 blocks of a parity class: one pass
+    (10, 1, 16, 64, "f32"),    # five among 16: passes of two slots
+    (64, 2, 8, 64, "bf16"),
+]
+
+
+@pytest.mark.parametrize("case", PER_BLOCK_CASES, ids=[f"p{c[0]}_v{c[1]}_tb{c[2]}_b{c[3]}_{c[4]}" for c in PER_BLOCK_CASES])
+def test_batched_sets_per_block(case):
+    period, vec, tb, batch, dtype = case
+    log(f"per-block sets {case}")
+    import dataclasses
+    wl = _fresh_small()
+    sched = np.repeat((np.arange(wl.n_calls) % period).astype(np.int32)[:, None], wl.n_channels, axis=1)
+    wl = dataclasses.replace(wl, schedule=sched)
+    conv = make_convolver(wl, dtype, max_batch=batch)
+    conv.configure_batch(chunk=0, vec=vec, waves=1, time_block=tb, group=1, engine=1)
+    got = gpu_streams(wl, dtype, conv=conv, batch=batch)
+    conv1 = make_convolver(wl, dtype)
+    one = gpu_streams(wl, dtype, conv=conv1, batch=1)
+    conv1.close()
+    conv.close()
+    ref = oracle_streams(wl, dtype=dtype)
+    err = rel_rms_per_channel(got, ref)
+    log(f"per-block sets {case}: rel-RMS {err.max():.3e}")
+    if dtype == "f32":
+        assert err.max() <= TOL_F32 and max_abs_err_per_channel(got, ref).max() <= ELEM_TOL_F32
+        assert rel_rms_per_channel(got, one).max() <= 1e-6
+    else:
+        assert err.max() <= 2e-4      # against the oracle with spectra rounded the same way
+        assert rel_rms_per_channel(got, one).max() <= 1e-6
+
+
 def test_taps_loaded_every_block_inside_a_graph():
     """Head tracking with responses arriving as taps: every call first loads
     the next set of every channel into a slot (tvolap_set_irs from device
