@@ -46,7 +46,9 @@ MFMA_16_PEAK_TFLOPS = 2500.0
 
 WORKLOADS = {
     "binaural": dict(desc="64 sources x 2 ears = 128 channels, L=256 (blocks 512, FFT 1024), 96000-tap IRs "
-                          "(188 partitions), 4 IR slots per channel switched every block, 5 s at 48 kHz",
+                          "(188 partitions), 4 recurring IR sets per channel, block l using set l mod 4 (a switch "
+                          "at every block; the same sets recur within a call), 5 s at 48 kHz; the "
+                          "fresh_response_sets legs give a new set at every block",
                      fn="binaural", dtype="f32"),
     "binaural_bf16": dict(desc="as binaural, IR spectra and delay line stored bf16", fn="binaural", dtype="bf16"),
     "binaural_f16": dict(desc="as binaural, IR spectra and delay line stored f16", fn="binaural", dtype="f16"),
