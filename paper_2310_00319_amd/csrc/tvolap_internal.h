@@ -88,8 +88,8 @@ hipError_t launch_inv(const DevPlan& P, int dtype, const float2* ypart, const vo
                       int32_t* sel_store, int32_t* done, uint64_t* counter, hipStream_t s);
 hipError_t launch_block(const BlockArgs& A, int dtype, const MacShape& shape, int grid, hipStream_t s);
 
-// Batches of consecutive blocks (k_batch_spectra, k_tmac, k_batch_inv,
-// k_batch_ola in tvolap_kernels.hip).
+// Batches of consecutive blocks (k_batch_spectra, k_tmac / k_tmfma,
+// k_batch_out in tvolap_kernels.hip).
 struct BatchArgs {
   DevPlan P;
   const WorkItem* items;       // time-blocked MAC items (partitions from 0)
