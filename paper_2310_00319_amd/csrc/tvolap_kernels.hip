@@ -141,6 +141,39 @@ __device__ __forceinline__ void load_vec_nt(const typename Store<DT>::T* __restr
   }
 }
 
+// 16-bit storage: V stored words as they are (16 bytes per lane where
+// possible), plain or with the non-temporal hint.
+template <int V, bool NT>
+__device__ __forceinline__ void load_words(const uint32_t* __restrict__ p, uint32_t (&w)[V]) {
+  if constexpr (V == 1) {
+    w[0] = p[0];
+  } else if constexpr (V == 2) {
+    const nt_u2 t = NT ? __builtin_nontemporal_load(reinterpret_cast<const nt_u2*>(p))
+                       : *reinterpret_cast<const nt_u2*>(p);
+    w[0] = t.x; w[1] = t.y;
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; j += 4) {
+      const nt_u4 t = NT ? __builtin_nontemporal_load(reinterpret_cast<const nt_u4*>(p + j))
+                         : *reinterpret_cast<const nt_u4*>(p + j);
+      w[j] = t.x; w[j + 1] = t.y; w[j + 2] = t.z; w[j + 3] = t.w;
+    }
+  }
+}
+
+// a.lo b.lo + a.hi b.hi + c in FP32 for two 16-bit values per word (bf16 for
+// DT 1, binary16 for DT 2); products of 16-bit values are exact in FP32.
+template <int DT>
+__device__ __forceinline__ float dot2w(uint32_t a, uint32_t b, float c) {
+  if constexpr (DT == 1) {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(b2, a), __builtin_bit_cast(b2, b), c, false);
+  } else {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, a), __builtin_bit_cast(h2, b), c, false);
+  }
+}
+
 // Device-coherent publication of partial spectra between workgroups of one
 // launch. Relaxed agent-scope atomic stores and loads of the 8-byte values are
 // performed at the device coherence point (they are not kept in, or served
@@ -296,29 +329,52 @@ __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[g][v] = make_float2(0.f, 0.f);
 
-  auto accumulate = [&](int g, const float2 (&H)[V], const float2 (&X)[V]) {
+  // f32: complex values, four FMAs per product. 16-bit: the stored words,
+  // two packed dot products per product (Re += (h.re, -h.im).(x.re, x.im),
+  // Im += (h.re, h.im).(x.im, x.re)), nothing unpacked.
+  using LW = std::conditional_t<DT == 0, float2, uint32_t>;
+  auto load_x = [&](const ST* p, LW (&o)[V]) {
+    if constexpr (DT == 0) load_vec<0, V>(p, o); else load_words<V, false>(p, o);
+  };
+  auto load_h = [&](const ST* p, LW (&o)[V]) {
+    if constexpr (DT == 0) load_vec_nt<0, V>(p, o); else load_words<V, true>(p, o);
+  };
+  auto accumulate = [&](int g, const LW (&H)[V], const LW (&X)[V]) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      float2 prod = cmul(H[v], X[v]);
-      if (v == 0 && dc_lane) prod = make_float2(H[0].x * X[0].x, H[0].y * X[0].y);
-      acc[g][v] = cadd(acc[g][v], prod);
+      if constexpr (DT == 0) {
+        float2 prod = cmul(H[v], X[v]);
+        if (v == 0 && dc_lane) prod = make_float2(H[0].x * X[0].x, H[0].y * X[0].y);
+        acc[g][v] = cadd(acc[g][v], prod);
+      } else {
+        const uint32_t h = H[v], x = X[v];
+        uint32_t hr = h ^ 0x80000000u, hi = h, xi = __builtin_amdgcn_alignbit(x, x, 16);
+        if (v == 0 && dc_lane) {
+          // packed (Re X(0), Re X(2L)): component-wise products
+          hr = h & 0xffffu;
+          hi = h & 0xffff0000u;
+          xi = x;
+        }
+        acc[g][v].x = dot2w<DT>(hr, x, acc[g][v].x);
+        acc[g][v].y = dot2w<DT>(hi, xi, acc[g][v].y);
+      }
     }
   };
   int m = (it.m0 > 1 ? it.m0 : 1) + w;
   for (; m + (U - 1) * NW < it.m1; m += U * NW) {
-    float2 X[U][V];
-    float2 H[U][G][V];
+    LW X[U][V];
+    LW H[U][G][V];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       int xr = q - (m + u * NW);
       if (xr < 0) xr += Mi;
-      load_vec<DT, V>(xbase + (uint32_t)(xr * N + kbase), X[u]);
+      load_x(xbase + (uint32_t)(xr * N + kbase), X[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int g = 0; g < G; ++g)
-        if (m + u * NW < Mc[g]) load_vec_nt<DT, V>(hbase[g] + (uint32_t)((m + u * NW) * N + kbase), H[u][g]);
+        if (m + u * NW < Mc[g]) load_h(hbase[g] + (uint32_t)((m + u * NW) * N + kbase), H[u][g]);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -328,13 +384,13 @@ __device__ __forceinline__ void mac_item(const DevPlan& P, const WorkItem& it,
   for (; m < it.m1; m += NW) {
     int xr = q - m;
     if (xr < 0) xr += Mi;
-    float2 X[V];
-    load_vec<DT, V>(xbase + (uint32_t)(xr * N + kbase), X);
+    LW X[V];
+    load_x(xbase + (uint32_t)(xr * N + kbase), X);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (m < Mc[g]) {
-        float2 H[V];
-        load_vec_nt<DT, V>(hbase[g] + (uint32_t)(m * N + kbase), H);
+        LW H[V];
+        load_h(hbase[g] + (uint32_t)(m * N + kbase), H);
         accumulate(g, H, X);
       }
     }
