@@ -1908,7 +1908,6 @@ __global__ __launch_bounds__(256) void k_batch_out(BatchArgs B, int W, const flo
   __shared__ float2 twl[2 * N];
   __shared__ float2 Zs[NWV][N];            // window sums, then the transforms' second buffer
   __shared__ float2 Fs[NWV][N];            // the transforms' first buffer
-  __shared__ float sto[3 * L];             // carried state of the previous call
   const DevPlan& P = B.P;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -1918,8 +1917,13 @@ __global__ __launch_bounds__(256) void k_batch_out(BatchArgs B, int W, const flo
   if (e < P.n_out) {
     for (int i = tid; i < 2 * N; i += T) twl[i] = P.tw[i];
     float* st = ola + (int64_t)e * 3 * L;
-    if (g == 0)
-      for (int i = tid; i < 3 * L; i += T) sto[i] = st[i];
+    // carried state of the previous call: window w < 3 is transformed by
+    // wave w in the first round of group 0, which keeps its L samples in
+    // registers (loaded before the barrier below, so before any wave stores
+    // new state)
+    float sto[L / 64];
+#pragma unroll
+    for (int i = 0; i < L / 64; ++i) sto[i] = (g == 0 && wv < 3) ? st[wv * L + lane + 64 * i] : 0.f;
     const int TW = B.tile_width;
     // the bus's spectrum rows: its first channel's rows (with a mixdown, that
     // channel's chunk-0 rows hold the bus sum), nsum rows per tile
@@ -1949,7 +1953,8 @@ __global__ __launch_bounds__(256) void k_batch_out(BatchArgs B, int W, const flo
       }
     };
     constexpr float scale = 1.0f / (float)(4 * L);
-    __syncthreads();   // twiddles and old state; the old state is read before any new one is stored
+    wait_memory();     // the old state is in registers before any wave can store the new one
+    __syncthreads();   // twiddles
 
     // One or two passes: the windows [w0, w1) from the blocks [b0, b1), all
     // of whose spectra are loaded first (at most W + 3 of them: every load of
@@ -2019,10 +2024,12 @@ __global__ __launch_bounds__(256) void k_batch_out(BatchArgs B, int W, const flo
           const float2* R = fft::fft_fwd<N, 64>(F, Z, twl, lane);
           const int w = w0 + v0 - 3 + wv;
           if (w >= w0 && w < w1) {
-            for (int t = lane; t < L; t += 64) {
+#pragma unroll
+            for (int i = 0; i < L / 64; ++i) {
+              const int t = lane + 64 * i;
               const float2 zz = R[t >> 1];
               float val = ((t & 1) ? -zz.y : zz.x) * scale;
-              if (w < 3) val += sto[w * L + t];
+              if (w < 3) val += sto[i];   // w < 3: wave w, group 0, first round
               if (w < n) out[(int64_t)e * out_stride + (int64_t)w * L + t] = val;
               else st[(w - n) * L + t] = val;   // new carried state
             }
